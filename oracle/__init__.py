@@ -1,0 +1,8 @@
+"""FP64 CPU oracle of the operator-splitting PPML update (arXiv:1607.01105).
+
+TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The GPU
+product path never imports, links or executes anything here, and this
+package imports nothing from the product package.
+"""
+from .oracle import Oracle, build, lib_path, load_library, reconstruct_line, avg_left, avg_right  # noqa: F401

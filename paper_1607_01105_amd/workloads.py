@@ -1,0 +1,298 @@
+"""Seeded synthetic inputs (primitive variables rho, v, p at cell centres).
+
+This module holds no arithmetic of the method: it only draws and lays out
+initial data, so that the GPU path and the CPU oracle can start from the
+same arrays.  Every generator returns a :class:`Problem` whose arrays are
+float64 numpy arrays in C order ``[z][y][x]`` (interior cells only).
+
+Generators and the paper's workloads they stand in for:
+
+* :func:`riemann_1d`     -- seeded 1-D Riemann problems (shock tubes of the
+  verification section, random left/right states).
+* :func:`shock_tube`     -- the three shock tubes of the paper's Table
+  "Initial state of the shock tube problem".
+* :func:`periodic_modes` -- 3-D (or 2-D) periodic box with a random-mode
+  density field and a central high-pressure sphere (Sedov-like blast in a
+  structured medium; the paper's blast and vacuum tests are 3-D boxes of
+  this kind).
+* :func:`disk`           -- rotating gaseous disk in a fixed logarithmic
+  potential (stand-in for the galactic-disk simulations; the paper's
+  equilibrium procedure and self-gravity are not reproduced).
+* :func:`aksenov`        -- smooth periodic Aksenov test (closed-form
+  solution).
+* :func:`advected_profile` -- smooth density advected by a uniform flow.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Problem:
+    name: str
+    ndim: int
+    n: tuple            # (nx, ny, nz); 1 for unused axes
+    lo: tuple
+    hi: tuple
+    gamma: float
+    cfl: float
+    bc: list            # per axis (lo, hi) names: "periodic" | "outflow" | "reflect"
+    rho: np.ndarray
+    vx: np.ndarray
+    vy: np.ndarray
+    vz: np.ndarray
+    p: np.ndarray
+    potential: tuple | None = None   # ("log", v0, rc, q, cx, cy, cz) | ("uniform", gx, gy, gz)
+    nsteps: int | None = None
+    t_stop: float | None = None
+
+    @property
+    def shape(self):
+        return (self.n[2], self.n[1], self.n[0])
+
+    @property
+    def cells(self) -> int:
+        return int(self.n[0] * self.n[1] * self.n[2])
+
+    def centres(self, axis: int) -> np.ndarray:
+        h = (self.hi[axis] - self.lo[axis]) / self.n[axis]
+        return self.lo[axis] + (np.arange(self.n[axis]) + 0.5) * h
+
+
+def _grid(ndim, n, lo, hi):
+    n = tuple(list(n) + [1] * (3 - len(n)))
+    lo = tuple(list(lo) + [-0.5] * (3 - len(lo)))
+    hi = tuple(list(hi) + [0.5] * (3 - len(hi)))
+    return n, lo, hi
+
+
+def _mesh(n, lo, hi):
+    xs = [lo[a] + (np.arange(n[a]) + 0.5) * (hi[a] - lo[a]) / n[a] for a in range(3)]
+    Z, Y, X = np.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
+    return X, Y, Z
+
+
+def riemann_states(seed: int):
+    """Left and right (rho, u, p): rho, p ~ U[0.1, 1], u ~ U[-1, 1], drawn in
+    the order rho_L, u_L, p_L, rho_R, u_R, p_R from numpy's PCG64."""
+    rng = np.random.default_rng(seed)
+    rL = rng.uniform(0.1, 1.0)
+    uL = rng.uniform(-1.0, 1.0)
+    pL = rng.uniform(0.1, 1.0)
+    rR = rng.uniform(0.1, 1.0)
+    uR = rng.uniform(-1.0, 1.0)
+    pR = rng.uniform(0.1, 1.0)
+    return (rL, uL, pL), (rR, uR, pR)
+
+
+def _two_state_1d(name, left, right, n, lo, hi, x0, gamma, cfl, bc, t_stop):
+    x = lo + (np.arange(n) + 0.5) * (hi - lo) / n
+    L = x < x0
+    rho = np.where(L, left[0], right[0]).astype(np.float64).reshape(1, 1, n)
+    u = np.where(L, left[1], right[1]).astype(np.float64).reshape(1, 1, n)
+    p = np.where(L, left[2], right[2]).astype(np.float64).reshape(1, 1, n)
+    z = np.zeros_like(rho)
+    return Problem(name, 1, (n, 1, 1), (lo, -0.5, -0.5), (hi, 0.5, 0.5), gamma, cfl,
+                   [(bc, bc), ("periodic", "periodic"), ("periodic", "periodic")],
+                   rho, u, z.copy(), z.copy(), p, None, None, t_stop)
+
+
+def riemann_1d(seed: int, n: int = 512, lo: float = 0.0, hi: float = 1.0, x0: float = 0.5,
+               gamma: float = 1.4, cfl: float = 0.4, t_stop: float = 0.15, bc: str = "outflow") -> Problem:
+    left, right = riemann_states(seed)
+    return _two_state_1d(f"riemann1d_s{seed}_n{n}", left, right, n, lo, hi, x0, gamma, cfl, bc, t_stop)
+
+
+# The paper's Table "Initial state of the shock tube problem":
+# (rho_L, v_L, p_L, rho_R, v_R, p_R, x0, t).  Copied in tests/golden too.
+SHOCK_TUBES = (
+    (1.0, 0.0, 1.0, 0.125, 0.0, 0.1, 0.5, 0.2),
+    (1.0, -2.0, 0.4, 1.0, 2.0, 0.4, 0.5, 0.15),
+    (1.0, 0.0, 1000.0, 1.0, 0.0, 0.01, 0.5, 0.012),
+)
+
+
+def shock_tube(k: int, n: int = 100, gamma: float = 1.4, cfl: float = 0.2) -> Problem:
+    rL, uL, pL, rR, uR, pR, x0, t = SHOCK_TUBES[k]
+    return _two_state_1d(f"shocktube{k + 1}_n{n}", (rL, uL, pL), (rR, uR, pR), n, 0.0, 1.0, x0,
+                         gamma, cfl, "outflow", t)
+
+
+def _mode_set(kmax: float, ndim: int):
+    r = int(math.floor(kmax))
+    ks = []
+    rng3 = range(-r, r + 1)
+    for kz in (rng3 if ndim == 3 else [0]):
+        for ky in (rng3 if ndim >= 2 else [0]):
+            for kx in rng3:
+                nrm = math.sqrt(kx * kx + ky * ky + kz * kz)
+                if 1.0 <= nrm <= kmax:
+                    ks.append((kx, ky, kz))
+    return ks
+
+
+def random_modes(rng, X, Y, Z, ndim, nmodes=8, kmax=4.0, amp=0.1):
+    """1 + amp * sum_m cos(2 pi k_m . x + phi_m), integer k_m uniform on
+    {1 <= |k| <= kmax}, phi_m ~ U[0, 2 pi)."""
+    ks = _mode_set(kmax, ndim)
+    idx = rng.integers(0, len(ks), size=nmodes)
+    phi = rng.uniform(0.0, 2.0 * math.pi, size=nmodes)
+    f = np.ones(X.shape)
+    for m in range(nmodes):
+        kx, ky, kz = ks[idx[m]]
+        f += amp * np.cos(2.0 * math.pi * (kx * X + ky * Y + kz * Z) + phi[m])
+    return f
+
+
+def periodic_modes(n: int | tuple = 256, seed: int = 0, ndim: int = 3, gamma: float = 5.0 / 3.0,
+                   cfl: float = 0.3, nsteps: int = 100, sphere_p: float = 100.0, sphere_r: float = 0.1,
+                   random_pressure: bool = False, sphere_centre=None) -> Problem:
+    """Periodic unit box: rho = random modes, p = 1 (or random modes) with a
+    high-pressure sphere, u = 0."""
+    if isinstance(n, int):
+        n = (n,) * ndim
+    n3, lo, hi = _grid(ndim, n, (0.0,) * ndim, (1.0,) * ndim)
+    X, Y, Z = _mesh(n3, lo, hi)
+    rng = np.random.default_rng(seed)
+    rho = random_modes(rng, X, Y, Z, ndim)
+    p = random_modes(rng, X, Y, Z, ndim) if random_pressure else np.ones(X.shape)
+    if sphere_p is not None and sphere_p > 0:
+        c = sphere_centre if sphere_centre is not None else (0.5, 0.5, 0.5)
+        d2 = (X - c[0]) ** 2
+        if ndim >= 2:
+            d2 = d2 + (Y - c[1]) ** 2
+        if ndim >= 3:
+            d2 = d2 + (Z - c[2]) ** 2
+        p = np.where(d2 <= sphere_r * sphere_r, sphere_p, p)
+    z = np.zeros(X.shape)
+    bc = [("periodic", "periodic")] * 3
+    return Problem(f"periodic{ndim}d_{'x'.join(map(str, n))}_s{seed}", ndim, n3, lo, hi, gamma, cfl, bc,
+                   np.ascontiguousarray(rho), z.copy(), z.copy(), z.copy(), np.ascontiguousarray(p),
+                   None, nsteps, None)
+
+
+def disk(nx: int = 512, ny: int = 512, nz: int = 64, seed: int = 0, v0: float = 1.0, rc: float = 0.02,
+         rd: float = 0.2, cs: float = 0.05, gamma: float = 5.0 / 3.0, cfl: float = 0.2, nsteps: int = 500,
+         rho_floor: float = 1e-3, noise: float = 0.01) -> Problem:
+    """Rotating gas disk in Phi = v0^2/2 ln(rc^2 + x^2 + y^2 + z^2), box
+    [-1/2,1/2]^2 x [-nz/(2 nx), nz/(2 nx)] (cubic cells): surface density
+    exp(-R/rd), vertical Gaussian of scale height max(cs/v0 sqrt(R^2+rc^2), 2h),
+    flat rotation v = v0 R / sqrt(R^2 + rc^2), p = rho cs^2 / gamma, 1% lognormal
+    density noise, outflow boundaries."""
+    h = 1.0 / nx
+    lo = (-0.5, -0.5 * ny * h, -0.5 * nz * h)
+    hi = (0.5, 0.5 * ny * h, 0.5 * nz * h)
+    n3 = (nx, ny, nz)
+    X, Y, Z = _mesh(n3, lo, hi)
+    R = np.sqrt(X * X + Y * Y)
+    sigma = np.exp(-R / rd)
+    H = np.maximum((cs / v0) * np.sqrt(R * R + rc * rc), 2.0 * h)
+    rho = sigma / (math.sqrt(2.0 * math.pi) * H) * np.exp(-Z * Z / (2.0 * H * H))
+    rho = np.maximum(rho, rho_floor)
+    rng = np.random.default_rng(seed)
+    rho = rho * np.exp(noise * rng.standard_normal(rho.shape))
+    vphi = v0 * R / np.sqrt(R * R + rc * rc)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        cx = np.where(R > 0, -Y / R, 0.0)
+        cy = np.where(R > 0, X / R, 0.0)
+    vx = vphi * cx
+    vy = vphi * cy
+    vz = np.zeros(X.shape)
+    p = rho * cs * cs / gamma
+    bc = [("outflow", "outflow")] * 3
+    pot = ("log", v0, rc, 1.0, 0.0, 0.0, 0.0)
+    return Problem(f"disk_{nx}x{ny}x{nz}_s{seed}", 3, n3, lo, hi, gamma, cfl, bc,
+                   np.ascontiguousarray(rho), np.ascontiguousarray(vx), np.ascontiguousarray(vy), vz,
+                   np.ascontiguousarray(p), pot, nsteps, None)
+
+
+def aksenov(n: int, cfl: float = 0.2) -> Problem:
+    """rho = 1 + 0.5 cos x on [0, 2 pi], u = 0, gamma = 3 and p = rho^3 / 3
+    (sound speed equal to rho), periodic."""
+    L = 2.0 * math.pi
+    x = (np.arange(n) + 0.5) * L / n
+    rho = (1.0 + 0.5 * np.cos(x)).reshape(1, 1, n)
+    p = rho ** 3 / 3.0
+    z = np.zeros_like(rho)
+    return Problem(f"aksenov_n{n}", 1, (n, 1, 1), (0.0, -0.5, -0.5), (L, 0.5, 0.5), 3.0, cfl,
+                   [("periodic", "periodic")] * 3, rho, z.copy(), z.copy(), z.copy(), p, None, None,
+                   0.5 * math.pi)
+
+
+def advected_profile(ndim: int, n: int, u0=(1.0, 0.5, 0.25), p0: float = 1.0, amp: float = 0.2,
+                     gamma: float = 1.4, cfl: float = 0.4, t_stop: float = 1.0) -> Problem:
+    """rho = 1 + amp sin(2 pi (x + y + z)) on the periodic unit box, uniform
+    velocity u0 and pressure p0: the exact solution is a translation."""
+    n3, lo, hi = _grid(ndim, (n,) * ndim, (0.0,) * ndim, (1.0,) * ndim)
+    X, Y, Z = _mesh(n3, lo, hi)
+    arg = X.copy()
+    if ndim >= 2:
+        arg = arg + Y
+    if ndim >= 3:
+        arg = arg + Z
+    rho = 1.0 + amp * np.sin(2.0 * math.pi * arg)
+    ones = np.ones(X.shape)
+    vx = u0[0] * ones
+    vy = (u0[1] if ndim >= 2 else 0.0) * ones
+    vz = (u0[2] if ndim >= 3 else 0.0) * ones
+    return Problem(f"advect{ndim}d_n{n}", ndim, n3, lo, hi, gamma, cfl, [("periodic", "periodic")] * 3,
+                   rho, vx, vy, vz, p0 * ones, None, None, t_stop)
+
+
+def uniform(ndim: int, n: int | tuple, rho0=1.0, v0=(0.3, -0.2, 0.1), p0=0.7, gamma=1.4, cfl=0.4,
+            bc="periodic") -> Problem:
+    if isinstance(n, int):
+        n = (n,) * ndim
+    n3, lo, hi = _grid(ndim, n, (0.0,) * ndim, (1.0,) * ndim)
+    shp = (n3[2], n3[1], n3[0])
+    ones = np.ones(shp)
+    return Problem(f"uniform{ndim}d", ndim, n3, lo, hi, gamma, cfl, [(bc, bc)] * 3, rho0 * ones,
+                   v0[0] * ones, (v0[1] if ndim >= 2 else 0.0) * ones, (v0[2] if ndim >= 3 else 0.0) * ones,
+                   p0 * ones, None, None, None)
+
+
+def random_smooth(ndim: int, n: int | tuple, seed: int, gamma=1.4, cfl=0.4, bc="periodic",
+                  vel_amp=0.3) -> Problem:
+    """Random-mode density and pressure, random-mode velocity components."""
+    if isinstance(n, int):
+        n = (n,) * ndim
+    n3, lo, hi = _grid(ndim, n, (0.0,) * ndim, (1.0,) * ndim)
+    X, Y, Z = _mesh(n3, lo, hi)
+    rng = np.random.default_rng(seed)
+    rho = random_modes(rng, X, Y, Z, ndim, amp=0.1)
+    p = random_modes(rng, X, Y, Z, ndim, amp=0.1)
+    vs = []
+    for a in range(3):
+        if a < ndim:
+            vs.append(vel_amp * (random_modes(rng, X, Y, Z, ndim, amp=0.1) - 1.0) * 10.0 / 8.0)
+        else:
+            vs.append(np.zeros(X.shape))
+    return Problem(f"smooth{ndim}d_s{seed}", ndim, n3, lo, hi, gamma, cfl, [(bc, bc)] * 3,
+                   rho, vs[0], vs[1], vs[2], p, None, None, None)
+
+
+def blocks(ndim: int, n: int | tuple, seed: int, gamma=1.4, cfl=0.4, bc="periodic") -> Problem:
+    """Piecewise-constant random blocks (discontinuities everywhere): exercises
+    every limiter branch."""
+    if isinstance(n, int):
+        n = (n,) * ndim
+    n3, lo, hi = _grid(ndim, n, (0.0,) * ndim, (1.0,) * ndim)
+    shp = (n3[2], n3[1], n3[0])
+    rng = np.random.default_rng(seed)
+
+    def field(lo_, hi_):
+        nb = [max(1, s // 4) for s in shp]
+        coarse = rng.uniform(lo_, hi_, size=nb)
+        f = coarse
+        for ax, s in enumerate(shp):
+            f = np.repeat(f, int(math.ceil(s / nb[ax])), axis=ax)
+        return np.ascontiguousarray(f[: shp[0], : shp[1], : shp[2]])
+
+    rho = field(0.2, 2.0)
+    p = field(0.2, 2.0)
+    vs = [field(-0.5, 0.5) if a < ndim else np.zeros(shp) for a in range(3)]
+    return Problem(f"blocks{ndim}d_s{seed}", ndim, n3, lo, hi, gamma, cfl, [(bc, bc)] * 3,
+                   rho, vs[0], vs[1], vs[2], p, None, None, None)
