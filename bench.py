@@ -1,0 +1,171 @@
+#!/usr/bin/env python3
+"""Benchmark of the PPML hot path on one MI355X.
+
+Workload (the headline configuration): 3-D 256^3 periodic unit cube,
+gamma = 5/3, density = 1 + 0.1 * (sum of 8 seeded random-phase Fourier modes
+with integer |k| <= 4), p = 1 with a p = 100 sphere of radius 0.1 at the
+centre, u = 0, CFL 0.3, 100 steps.  FP32 state (FP64 totals and energy
+recovery) is the headline value; the FP64 run is reported beside it with the
+L1 distance of the two densities after the run.
+
+A step is one full pass of the method: Eulerian kernel + Lagrangian kernel
+(energy correction and CFL maxima fused).  The state is resident in HBM
+when the timed region starts; the K timed steps start from the initial state
+(the warm-up steps are discarded by re-setting it) and are bracketed by
+device synchronisation and HIP events on the solver's stream.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+WORKLOAD = ("3D 256^3 periodic unit cube, gamma 5/3, rho = 1 + 0.1 * 8 random modes (|k| <= 4), "
+            "p = 1 with p = 100 sphere r = 0.1 at centre, u = 0, CFL 0.3, 100 steps")
+
+
+def algorithmic_bytes_per_zone(kernel: str, ndim: int, width: int) -> int:
+    """Compulsory HBM bytes of one kernel per zone: the Eulerian kernel reads
+    the F = 3 + ndim conserved fields and writes the F - 1 it changes (rho is
+    unchanged); the Lagrangian kernel reads F fields and writes F."""
+    F = 3 + ndim
+    return (2 * F - 1) * width if kernel == "euler" else 2 * F * width
+
+
+def run_precision(prob, prec, steps, warmup):
+    import torch
+
+    from paper_1607_01105_amd.ppml import Grid
+
+    g = Grid.from_problem(prob, prec=prec, device="cuda:0")
+    if warmup > 0:
+        g.step(warmup)
+        g.sync()
+        g.set_primitive(prob.rho, prob.vx, prob.vy, prob.vz, prob.p)
+    g.set_timing(steps)
+    stream = g.stream
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    g.step(steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    me, ml, nt = g.get_timing()
+    g.sync()
+    t, dt, taken = g.time()
+    rho = g.get("rho")
+    tot = g.totals()
+    del g
+    torch.cuda.empty_cache()
+    return dict(ms=ms, ms_euler=me / max(nt, 1), ms_lagr=ml / max(nt, 1), timed_steps=nt, t=t, steps_taken=taken,
+                rho=rho, totals=tot)
+
+
+def cpu_baseline(prob, max_seconds=30.0):
+    """The FP64 oracle, untuned, on this host's cores: one step of the full
+    256^3 workload (16.8M zone-updates)."""
+    import oracle
+
+    o = oracle.Oracle(prob.ndim, prob.n, prob.lo, prob.hi, prob.gamma, prob.cfl, bc=prob.bc)
+    o.set_primitive(prob.rho, prob.vx, prob.vy, prob.vz, prob.p)
+    tau = o.dt()
+    t0 = time.perf_counter()
+    o.step(tau)
+    sec = time.perf_counter() - t0
+    cores = oracle.max_threads()
+    del o
+    return {"value": prob.cells / sec, "unit": "zone-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"one step of the same 256^3 workload ({prob.cells} zone-updates), FP64, {sec:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
+              "described in DESIGN.md and not run", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1607_01105_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    prob = W.periodic_modes(args.n, seed=0)
+    cells = prob.cells
+    res = {}
+    for prec in ("fp32", "fp64"):
+        if args.only and prec != args.only:
+            continue
+        print(f"[bench] {prec} {args.n}^3 steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
+        res[prec] = run_precision(prob, prec, args.steps, args.warmup)
+        r = res[prec]
+        print(f"[bench] {prec}: {r['ms'] / args.steps:.3f} ms/step, euler {r['ms_euler']:.3f} ms, "
+              f"lagr {r['ms_lagr']:.3f} ms, {cells * args.steps / (r['ms'] * 1e-3):.3e} zu/s",
+              file=sys.stderr, flush=True)
+
+    head = "fp32" if "fp32" in res else "fp64"
+    r = res[head]
+    value = cells * args.steps / (r["ms"] * 1e-3)
+    width = 4 if head == "fp32" else 8
+    # dominant kernel and its HBM roofline
+    kern = "lagr" if r["ms_lagr"] >= r["ms_euler"] else "euler"
+    ms_k = r["ms_" + kern]
+    bytes_launch = algorithmic_bytes_per_zone(kern, 3, width) * cells
+    achieved = bytes_launch / (ms_k * 1e-3) / 1e9
+    out = {
+        "metric": "zone-updates/sec FP32 vs FP64 at stated L1 error; p50/p99 latency when served",
+        "value": value,
+        "unit": "zone-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if head == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "grid": [args.n] * 3, "gamma": 5.0 / 3.0, "cfl": 0.3, "seed": 0,
+                   "state": head},
+        "kernels_ms": {"euler": r["ms_euler"], "lagr": r["ms_lagr"]},
+        "roofline": {"bound": "hbm", "kernel": "k_" + kern, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_zone": algorithmic_bytes_per_zone(kern, 3, width)},
+    }
+    if "fp64" in res and "fp32" in res:
+        import numpy as np
+
+        r64 = res["fp64"]
+        out["fp64"] = {"value": cells * args.steps / (r64["ms"] * 1e-3), "ms_per_step": r64["ms"] / args.steps,
+                       "kernels_ms": {"euler": r64["ms_euler"], "lagr": r64["ms_lagr"]}}
+        out["l1_rho_fp32_vs_fp64"] = float(np.sum(np.abs(res["fp32"]["rho"] - r64["rho"])) / np.sum(np.abs(r64["rho"])))
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

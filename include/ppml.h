@@ -1,0 +1,171 @@
+/*
+ * ppml.h -- C ABI of the MI355X solver for the operator-splitting PPML
+ * scheme of Kulikov & Vorobyov, "Using the PPML approach for constructing a
+ * low-dissipation, operator-splitting scheme for numerical simulations of
+ * hydrodynamic flows" (arXiv:1607.01105).
+ *
+ * The problem follows the paper's statement (Sec. 2, eqs. (1)-(4)): the
+ * unknowns are the densities of mass rho, momentum rho*v, total energy
+ * rho*E and internal energy rho*eps of an ideal gas with p = (gamma-1) rho eps,
+ * on a uniform Cartesian mesh, optionally in a fixed external potential Phi,
+ * advanced with the CFL time step of Sec. 2.1.  One step = Eulerian stage
+ * (acoustic Riemann problem on parabolas, pressure and force terms, no
+ * advection; Sec. 2.1-2.2) + Lagrangian stage (upwind parabolic advection
+ * with the 9-point transverse velocity; Sec. 2.3) + total-energy correction
+ * (Sec. 2.4).  Every step runs in HIP kernels on the caller's stream.
+ *
+ * Conventions shared by every function:
+ *  - Return value: PPML_OK (0) or a negative ppml_status.  Nothing throws
+ *    across the ABI.  ppml_last_error() gives a thread-local detail string.
+ *  - Memory: the caller owns all device memory and the HIP stream; the
+ *    library borrows the pointers for the lifetime of the grid and owns only
+ *    the small opaque host object (and short-lived staging buffers inside
+ *    the set/get calls).
+ *  - Device state layout (structure of arrays, x fastest, C order
+ *    [z][y][x]): F = 3 + ndim fields of n[0]*n[1]*n[2] values of the storage
+ *    type (float for PPML_FP32, double for PPML_FP64), in the order
+ *    rho, rho*vx [, rho*vy [, rho*vz]], rho*E, rho*eps.
+ *  - Host arrays are FP64, interior cells only, C order [z][y][x].
+ *  - Asynchrony: ppml_step only enqueues work; functions that return values
+ *    to the host (get_*, totals, sync) synchronize the stream first.
+ */
+#ifndef PPML_H
+#define PPML_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PPML_OK = 0,
+    PPML_EINVAL = -1,     /* bad descriptor, argument or initial state      */
+    PPML_ENOMEM = -2,     /* staging allocation failed                      */
+    PPML_EHIP = -3,       /* a HIP runtime call failed                      */
+    PPML_ENONFINITE = -4, /* a step produced rho <= 0, eps <= 0 or NaN/Inf  */
+    PPML_EBUDGET = -5,    /* request exceeds the memory budget              */
+    PPML_ESTATE = -6      /* call not valid in the object's current state   */
+} ppml_status;
+
+typedef enum { PPML_FP32 = 0, PPML_FP64 = 1 } ppml_precision;
+
+/* Boundary conditions (the paper names periodic, outflow and reflecting
+ * walls in its tests; their ghost-cell form is a reading: periodic = wrap,
+ * outflow = copy of the nearest interior cell, reflect = mirror image with
+ * the wall-normal momentum negated; three ghost layers per side). */
+typedef enum { PPML_PERIODIC = 0, PPML_OUTFLOW = 1, PPML_REFLECT = 2 } ppml_bc;
+
+/* Conserved fields (Sec. 2, eqs. (1)-(4)). */
+typedef enum { PPML_RHO = 0, PPML_MX = 1, PPML_MY = 2, PPML_MZ = 3, PPML_ETOT = 4, PPML_EINT = 5 } ppml_field;
+
+/* Fixed external potential whose gradient enters the momentum and energy
+ * equations (eqs. (2)-(3)):
+ *   PPML_POT_LOG:     Phi = v0^2/2 ln(rc^2 + X^2 + Y^2 + Z^2/q^2), X = x - cx, ...
+ *                     pot = {v0, rc, q, cx, cy, cz}
+ *   PPML_POT_UNIFORM: Phi = gx x + gy y + gz z;  pot = {gx, gy, gz}      */
+typedef enum { PPML_POT_NONE = 0, PPML_POT_LOG = 1, PPML_POT_UNIFORM = 2 } ppml_potential;
+
+typedef struct {
+    int32_t ndim;          /* 1, 2 or 3                                             */
+    int32_t prec;          /* ppml_precision of the stored state and the stencil    */
+    int64_t n[3];          /* interior cells per axis; 1 for axes >= ndim           */
+    double lo[3], hi[3];   /* domain extents; cell size h[d] = (hi-lo)/n            */
+    double gamma;          /* ratio of specific heats, > 1                          */
+    double cfl;            /* Courant number, 0 < cfl < 1 (the paper uses 0.2)      */
+    int32_t bc_lo[3];      /* ppml_bc of the low face of each axis                  */
+    int32_t bc_hi[3];      /* ppml_bc of the high face                              */
+    double vacuum_ratio;   /* Sec. 2.4 vacuum threshold relative to the initial
+                              mean density (the paper: five orders, 1e-5)            */
+    int32_t potential;     /* ppml_potential                                        */
+    int32_t reserved;      /* must be 0                                             */
+    double pot[8];         /* potential parameters (see ppml_potential)             */
+} ppml_desc;
+
+typedef struct ppml_grid ppml_grid;
+
+/* Bytes of device memory the caller must provide for the state
+ * ((3+ndim) * cells * sizeof(storage type)) and for the scratch area (the
+ * Eulerian-stage output, the control block and reduction partials).
+ * Returns 0 for an invalid descriptor. */
+size_t ppml_state_bytes(const ppml_desc *d);
+size_t ppml_scratch_bytes(const ppml_desc *d);
+
+/* Create a grid on the current HIP device.  state_dev and scratch_dev are
+ * device pointers of at least ppml_state_bytes / ppml_scratch_bytes bytes,
+ * 256-byte aligned; hip_stream is a hipStream_t (NULL = default stream).
+ * The state is undefined until ppml_set_primitive or ppml_set_conserved.
+ * Errors: PPML_EINVAL (descriptor: ndim, n >= 1, reflect needs n >= 3,
+ * gamma > 1, 0 < cfl < 1, extents, enums), PPML_EHIP. */
+int ppml_create(const ppml_desc *d, void *state_dev, void *scratch_dev, void *hip_stream, ppml_grid **out);
+
+/* Set the state from primitive variables at cell centres (Sec. 2): e = p/(gamma-1),
+ * rho*E = e + rho |v|^2 / 2, computed in FP64 on the device and rounded to the
+ * storage type.  vy / vz may be NULL (zero); components of axes >= ndim are
+ * ignored.  Resets the time to 0, the step count to 0, records the FP64 mean
+ * density for the vacuum threshold and computes the first CFL maxima.
+ * Errors: PPML_EINVAL (NULL rho/p, rho <= 0 or p <= 0 or non-finite values),
+ * PPML_ENOMEM, PPML_EHIP. */
+int ppml_set_primitive(ppml_grid *g, const double *rho, const double *vx, const double *vy, const double *vz,
+                       const double *p);
+
+/* Set the conserved fields directly (checkpoint restore): f[ppml_field]
+ * host arrays, entries of unused momentum axes may be NULL.  rho_mean0 > 0
+ * sets the vacuum reference density (<= 0: mean of the given rho); t sets
+ * the time.  Errors as ppml_set_primitive. */
+int ppml_set_conserved(ppml_grid *g, const double *const *f, double rho_mean0, double t);
+
+/* Enqueue nsteps steps.  dt_fixed > 0: use that time step; otherwise the CFL
+ * step tau = cfl * min_d h_d / (max|v| + max c) of the current state (maxima
+ * taken separately, Sec. 2.1).  t_stop > 0: clip the step so the run ends at
+ * t_stop; steps after that are no-ops.  Asynchronous: errors of the step
+ * itself are reported by the next synchronizing call.
+ * Errors: PPML_EINVAL (nsteps < 0), PPML_ESTATE (state never set), PPML_EHIP. */
+int ppml_step(ppml_grid *g, int32_t nsteps, double dt_fixed, double t_stop);
+
+/* Synchronize and read the time, the last time step and the number of
+ * steps taken (any pointer may be NULL).  Returns PPML_ENONFINITE if a step
+ * produced a non-physical value. */
+int ppml_get_time(ppml_grid *g, double *t, double *dt_last, int64_t *steps);
+
+/* Synchronize and read the current maxima of |v| and of c over the cells. */
+int ppml_max_speeds(ppml_grid *g, double *vmax, double *cmax);
+
+/* Synchronize and copy one conserved field to host_out (FP64, cells values).
+ * Errors: PPML_EINVAL (field of an unused axis), PPML_ENOMEM, PPML_EHIP. */
+int ppml_get_conserved(ppml_grid *g, int32_t field, double *host_out);
+
+/* Synchronize and return the FP64 sums over all cells of the six conserved
+ * densities (unused momentum axes give 0); the summation order is fixed,
+ * so repeated calls on the same state give identical bits. */
+int ppml_totals(ppml_grid *g, double out[6]);
+
+/* Synchronize the grid's stream; PPML_ENONFINITE if a step failed. */
+int ppml_sync(ppml_grid *g);
+
+/* Destroy the host object (does not free caller memory). */
+int ppml_destroy(ppml_grid *g);
+
+/* Static description of the status code; thread-local detail of the last error. */
+const char *ppml_strerror(int status);
+const char *ppml_last_error(void);
+
+/* Per-kernel timing of ppml_step, for benchmarks.  ppml_set_timing(g, cap)
+ * with cap > 0 creates HIP events for up to cap steps and makes ppml_step
+ * record an event before the Eulerian kernel, between the two stage kernels
+ * and after the Lagrangian kernel on the grid's stream (steps beyond cap
+ * are not timed); cap = 0 turns timing off and releases the events.
+ * ppml_get_timing synchronizes, returns the summed kernel durations in
+ * milliseconds (event-to-event on the same stream) and the number of steps
+ * timed, and starts a new accumulation.  Errors: PPML_EINVAL, PPML_EHIP. */
+int ppml_set_timing(ppml_grid *g, int32_t cap);
+int ppml_get_timing(ppml_grid *g, double *ms_euler, double *ms_lagr, int64_t *nsteps);
+
+/* Library version (major*10000 + minor*100 + patch). */
+int ppml_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PPML_H */

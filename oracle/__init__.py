@@ -5,4 +5,5 @@ TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 product path never imports, links or executes anything here, and this
 package imports nothing from the product package.
 """
-from .oracle import Oracle, build, lib_path, load_library, reconstruct_line, avg_left, avg_right  # noqa: F401
+from .oracle import (Oracle, avg_left, avg_right, build, lib_path, load_library, max_threads,  # noqa: F401
+                     reconstruct_line)

@@ -76,6 +76,8 @@ def load_library(path: str | None = None) -> C.CDLL:
     lib.og_reconstruct_line.argtypes = [dp, C.c_long, dp, dp, dp, dp, dp]
     lib.og_avg_left.restype = C.c_double
     lib.og_avg_left.argtypes = [C.c_double] * 4
+    lib.og_max_threads.restype = C.c_int
+    lib.og_max_threads.argtypes = []
     lib.og_avg_right.restype = C.c_double
     lib.og_avg_right.argtypes = [C.c_double] * 4
     _cache[path] = lib
@@ -88,6 +90,11 @@ def _dp(a: np.ndarray):
 
 def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def max_threads(lib: C.CDLL | None = None) -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int((lib or load_library()).og_max_threads())
 
 
 def reconstruct_line(q, lib: C.CDLL | None = None):

@@ -712,3 +712,11 @@ long og_run(og_grid *g, long nsteps, double dt_fixed, double t_stop, double *tau
     }
     return taken;
 }
+
+/* Threads the oracle's parallel loops use (for reporting). */
+#ifdef _OPENMP
+#include <omp.h>
+int og_max_threads(void) { return omp_get_max_threads(); }
+#else
+int og_max_threads(void) { return 1; }
+#endif

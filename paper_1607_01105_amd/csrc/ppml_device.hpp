@@ -1,0 +1,293 @@
+// ppml_device.hpp -- device-side building blocks of the PPML update for
+// gfx950 (CDNA4): parameters, boundary index maps, parabola construction
+// (Appendix, steps 1-3), characteristic averages (Appendix), the
+// modified-Roe acoustic Riemann solver (Sec. 2.1-2.2) and the upwind
+// parabolic flux (Sec. 2.3).
+//
+// Arithmetic notes.  With PPML_EXACT defined the build uses no FMA
+// contraction and divides wherever the scheme's formulas divide, in the
+// formulas' own operation order, so an FP64 build reproduces an
+// IEEE-754 evaluation of the formulas operation by operation.  The normal
+// build lets the compiler contract multiply-adds and replaces divisions by
+// constants and cell sizes with multiplications by precomputed inverses.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ppml {
+
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2 };
+enum { POT_NONE = 0, POT_LOG = 1, POT_UNIFORM = 2 };
+constexpr int GH = 3;  // ghost layers: a cell update reads q[i-3 .. i+3]
+
+// Per-grid constants passed by value to every kernel.
+struct GridParams {
+    int ndim;
+    int n[3];
+    long long ncell;
+    double h[3], inv_h[3];
+    double lo[3];
+    double gamma;
+    double cfl_hmin;      // cfl * min over active axes of h
+    double vacuum_ratio;  // threshold relative to the initial mean density
+    int bc_lo[3], bc_hi[3];
+    int potential;
+    double pot[8];
+};
+
+// Device control block of one grid (lives in the scratch area).
+struct Ctrl {
+    double t;             // simulation time
+    double tau;           // time step of the step in flight
+    double rho_mean0;     // FP64 initial mean density (vacuum reference)
+    double dt_last;       // last time step taken
+    unsigned long long vmax_bits[2];  // max |v| of the state, as FP64 bits (two slots)
+    unsigned long long cmax_bits[2];  // max c, as FP64 bits
+    long long steps;      // steps taken
+    int err;              // sticky error word (bit 0: non-physical state)
+    int pad;
+};
+
+struct StepArgs {
+    double dt_fixed;  // > 0: fixed time step
+    double t_stop;    // > 0: clip to end at t_stop
+    int slot;         // slot holding the maxima of the step's input state
+};
+
+#ifdef PPML_EXACT
+#define PPML_DIV(a, b, inv_b) ((a) / (b))
+#else
+#define PPML_DIV(a, b, inv_b) ((a) * (inv_b))
+#endif
+
+template <typename T> struct K {
+    static constexpr T half = T(0.5);
+    static constexpr T two = T(2);
+    static constexpr T three = T(3);
+    static constexpr T six = T(6);
+    static constexpr T inv3 = T(1) / T(3);
+    static constexpr T inv6 = T(1) / T(6);
+};
+
+__device__ __forceinline__ float dsqrt(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double dsqrt(double x) { return __builtin_sqrt(x); }
+__device__ __forceinline__ float dabs(float x) { return __builtin_fabsf(x); }
+__device__ __forceinline__ double dabs(double x) { return __builtin_fabs(x); }
+__device__ __forceinline__ float dcopysign(float m, float s) { return __builtin_copysignf(m, s); }
+__device__ __forceinline__ double dcopysign(double m, double s) { return __builtin_copysign(m, s); }
+__device__ __forceinline__ float dmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ double dmin(double a, double b) { return __builtin_fmin(a, b); }
+
+// Index of the interior cell that supplies the value at index i (which may
+// lie in a ghost layer or, for cells of a partial tile, further out) along
+// an axis of n cells; flip = 1 when the wall-normal momentum changes sign.
+__device__ __forceinline__ int map_index(int i, int n, int bclo, int bchi, int &flip)
+{
+    flip = 0;
+    if (i < 0) {
+        if (bclo == BC_PERIODIC) {
+            int r = i % n;
+            return r < 0 ? r + n : r;
+        }
+        if (bclo == BC_OUTFLOW) return 0;
+        flip = 1;
+        int r = -1 - i;
+        return r < n ? r : n - 1;
+    }
+    if (i >= n) {
+        if (bchi == BC_PERIODIC) return i % n;
+        if (bchi == BC_OUTFLOW) return n - 1;
+        flip = 1;
+        int r = 2 * n - 1 - i;
+        return r >= 0 ? r : 0;
+    }
+    return i;
+}
+
+// Appendix step 1: limited slope delta_m q of the middle value.
+template <typename T> __device__ __forceinline__ T limited_slope(T qm, T q0, T qp)
+{
+    T dq = K<T>::half * (qp - qm);
+    T dplus = qp - q0;
+    T dminus = q0 - qm;
+    T m = dmin(dabs(dq), dmin(K<T>::two * dabs(dplus), K<T>::two * dabs(dminus)));
+    return (dplus * dminus > T(0)) ? dcopysign(m, dq) : T(0);
+}
+
+// Appendix step 1: fourth-order interface value between q0 and q1.
+template <typename T> __device__ __forceinline__ T interface_value(T q0, T q1, T dm0, T dm1)
+{
+#ifdef PPML_EXACT
+    return K<T>::half * (q0 + q1) - (dm1 - dm0) / K<T>::six;
+#else
+    return K<T>::half * (q0 + q1) - (dm1 - dm0) * K<T>::inv6;
+#endif
+}
+
+// Appendix steps 2-3: monotonize the parabola of a cell with value c and
+// edge values l, r; returns (L, R, Q6) with Q6 = 6 (c - (L + R)/2).  The
+// jump across the cell is R - L.
+template <typename T> struct Parab {
+    T L, R, Q6;
+};
+
+template <typename T> __device__ __forceinline__ Parab<T> monotonize(T c, T l, T r)
+{
+    if ((r - c) * (c - l) <= T(0)) {
+        l = c;
+        r = c;
+    } else {
+        T d = r - l;
+        T s6 = K<T>::six * (c - K<T>::half * (l + r));
+        T ds = d * s6, dd = d * d;
+        if (ds > dd)
+            l = K<T>::three * c - K<T>::two * r;
+        else if (ds < -dd)
+            r = K<T>::three * c - K<T>::two * l;
+    }
+    Parab<T> p;
+    p.L = l;
+    p.R = r;
+    p.Q6 = K<T>::six * (c - K<T>::half * (l + r));
+    return p;
+}
+
+// Full parabola of the middle cell of five consecutive values.
+template <typename T> __device__ __forceinline__ Parab<T> parabola5(T qm2, T qm1, T q0, T qp1, T qp2)
+{
+    T dmm = limited_slope(qm2, qm1, q0);
+    T dm0 = limited_slope(qm1, q0, qp1);
+    T dmp = limited_slope(q0, qp1, qp2);
+    T l = interface_value(qm1, q0, dmm, dm0);
+    T r = interface_value(q0, qp1, dm0, dmp);
+    return monotonize(q0, l, r);
+}
+
+// Appendix: mean of a cell's parabola over the strip of z*h next to its
+// right edge (q_L(-lambda t)) and next to its left edge (q_R(lambda t)).
+template <typename T> __device__ __forceinline__ T curv_weight(T z)
+{
+#ifdef PPML_EXACT
+    return T(1) - (K<T>::two * z) / K<T>::three;
+#else
+    return T(1) - (K<T>::two * z) * K<T>::inv3;
+#endif
+}
+template <typename T> __device__ __forceinline__ T avg_left(T L, T R, T Q6, T z)
+{
+    T d = R - L;
+    T w = curv_weight(z);
+    return R - (K<T>::half * z) * (d - Q6 * w);
+}
+template <typename T> __device__ __forceinline__ T avg_right(T L, T R, T Q6, T z)
+{
+    T d = R - L;
+    T w = curv_weight(z);
+    return L + (K<T>::half * z) * (d + Q6 * w);
+}
+
+// Sec. 2.1-2.2: acoustic Riemann problem at the interface between cells a
+// (left) and b (right).  s = sqrt(rho), r32 = rho * s, ps = p * s are the
+// cell-centre values; (vL, pL) and (vR, pR) the parabolas of the normal
+// velocity and the pressure of the two cells.  Returns V and P.
+template <typename T> struct VP {
+    T V, P;
+};
+
+template <typename T>
+__device__ __forceinline__ VP<T> riemann(T sa, T sb, T r32a, T r32b, T psa, T psb, const Parab<T> &va,
+                                         const Parab<T> &vb, const Parab<T> &pa, const Parab<T> &pb, T gamma,
+                                         T tau, T h, T tau_over_h)
+{
+    T A = r32a + r32b;
+    T B = sa + sb;
+    T C = psa + psb;
+    T lam = dsqrt(gamma * C / A);
+    T Z = dsqrt(gamma * A * C) / B;
+#ifdef PPML_EXACT
+    T z = lam * tau / h;
+#else
+    (void)tau;
+    (void)h;
+    T z = lam * tau_over_h;
+#endif
+    T vm = avg_left(va.L, va.R, va.Q6, z);
+    T vp = avg_right(vb.L, vb.R, vb.Q6, z);
+    T pm = avg_left(pa.L, pa.R, pa.Q6, z);
+    T pp = avg_right(pb.L, pb.R, pb.Q6, z);
+    VP<T> o;
+    o.V = K<T>::half * (vm + vp) + (pm - pp) / (K<T>::two * Z);
+    o.P = K<T>::half * (pm + pp) + (K<T>::half * Z) * (vm - vp);
+    return o;
+}
+
+// Sec. 2.3: upwind flux of one field through an interface with velocity vh;
+// a is the cell on the left, b on the right.
+template <typename T> __device__ __forceinline__ T upwind_flux(T vh, T z, const Parab<T> &a, const Parab<T> &b)
+{
+    T fs = (vh >= T(0)) ? avg_left(a.L, a.R, a.Q6, z) : avg_right(b.L, b.R, b.Q6, z);
+    return vh * fs;
+}
+
+// Density-weighted interface velocity (Sec. 2.3).
+template <typename T> __device__ __forceinline__ T interface_velocity(T va, T sa, T vb, T sb)
+{
+    return (va * sa + vb * sb) / (sa + sb);
+}
+
+// Gradient of the fixed potential at a cell centre (eqs. (2)-(3) force terms).
+__device__ __forceinline__ void potential_grad(const GridParams &gp, int i, int j, int k, double g[3])
+{
+    double x = gp.lo[0] + ((double)i + 0.5) * gp.h[0];
+    double y = gp.lo[1] + ((double)j + 0.5) * gp.h[1];
+    double z = gp.lo[2] + ((double)k + 0.5) * gp.h[2];
+    if (gp.potential == POT_LOG) {
+        double v0 = gp.pot[0], rc = gp.pot[1], q = gp.pot[2];
+        double X = x - gp.pot[3], Y = y - gp.pot[4], Z = z - gp.pot[5];
+        double q2 = q * q;
+        double den = rc * rc + X * X + Y * Y + Z * Z / q2;
+        double a = v0 * v0 / den;
+        g[0] = a * X;
+        g[1] = a * Y;
+        g[2] = a * (Z / q2);
+    } else if (gp.potential == POT_UNIFORM) {
+        g[0] = gp.pot[0];
+        g[1] = gp.pot[1];
+        g[2] = gp.pot[2];
+    } else {
+        g[0] = g[1] = g[2] = 0.0;
+    }
+    for (int a = gp.ndim; a < 3; a++) g[a] = 0.0;
+}
+
+__device__ __forceinline__ double compute_tau(const Ctrl *c, const GridParams &gp, const StepArgs &sa)
+{
+    double tau;
+    if (sa.dt_fixed > 0.0) {
+        tau = sa.dt_fixed;
+    } else {
+        double vm = __longlong_as_double((long long)c->vmax_bits[sa.slot]);
+        double cm = __longlong_as_double((long long)c->cmax_bits[sa.slot]);
+        tau = gp.cfl_hmin / (vm + cm);
+    }
+    if (sa.t_stop > 0.0) {
+        double rem = sa.t_stop - c->t;
+        if (rem <= 0.0) tau = 0.0;
+        else if (tau > rem) tau = rem;
+    }
+    return tau;
+}
+
+// Wave-wide maximum (wave64).
+template <typename T> __device__ __forceinline__ T wave_max(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        T w = __shfl_xor(v, o, 64);
+        v = v > w ? v : w;
+    }
+    return v;
+}
+
+}  // namespace ppml

@@ -1,0 +1,762 @@
+// ppml_kernels.hip -- HIP kernels of the PPML operator-splitting update on
+// gfx950.  One step is two fused kernels:
+//
+//   k_euler : Eulerian stage (Sec. 2.1-2.2): reconstruct v_d and p along
+//             every axis, acoustic Riemann problem on parabolas at every
+//             interface, unsplit update of rho v, rho E, rho eps plus the
+//             external force.  U^n -> U^{n+1/2}.
+//   k_lagr  : Lagrangian stage (Sec. 2.3): 9-point transverse velocity,
+//             density-weighted interface velocity, upwind parabolic fluxes
+//             of all conserved densities, unsplit update; then the
+//             total-energy correction (Sec. 2.4) and the per-wave maxima of
+//             |v| and c for the next CFL step (Sec. 2.1).  U^{n+1/2} -> U^{n+1}.
+//
+// Work decomposition (3-D): a workgroup owns a TX x TY column tile in (x, y)
+// and marches along z over a chunk of planes.  The x and y directions of each
+// plane are computed from LDS tiles with a 3-cell halo; the z direction is a
+// per-thread register pipeline over the thread's own column (loads run three
+// planes ahead), so no z halo is ever staged.  2-D and 1-D grids use the same
+// kernels with one plane (and TY = 1 in 1-D).
+#include "ppml_device.hpp"
+
+namespace ppml {
+
+template <typename T> __device__ __forceinline__ T ldg(const T *p) { return __builtin_nontemporal_load(p); }
+
+// ---------------------------------------------------------------------------
+// State initialisation and conversion kernels
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_prim_to_cons(const double *__restrict__ prim, T *__restrict__ U, GridParams gp)
+{
+    const long long N = gp.ncell;
+    const int nd = gp.ndim;
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x) {
+        double r = prim[c];
+        double ux = prim[N + c];
+        double uy = nd >= 2 ? prim[2 * N + c] : 0.0;
+        double uz = nd >= 3 ? prim[3 * N + c] : 0.0;
+        double p = prim[4 * N + c];
+        double e = p / (gp.gamma - 1.0);
+        double ke = 0.5 * r * (ux * ux + uy * uy + uz * uz);
+        U[c] = (T)r;
+        U[N + c] = (T)(r * ux);
+        if (nd >= 2) U[2 * N + c] = (T)(r * uy);
+        if (nd >= 3) U[3 * N + c] = (T)(r * uz);
+        U[(1 + nd) * N + c] = (T)(e + ke);
+        U[(2 + nd) * N + c] = (T)e;
+    }
+}
+
+template <typename T> __global__ void k_from_double(const double *__restrict__ src, T *__restrict__ dst, long long n)
+{
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x)
+        dst[c] = (T)src[c];
+}
+
+template <typename T> __global__ void k_to_double(const T *__restrict__ src, double *__restrict__ dst, long long n)
+{
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x)
+        dst[c] = (double)src[c];
+}
+
+__global__ void k_ctrl_reset(Ctrl *ctrl, double t)
+{
+    ctrl->t = t;
+    ctrl->tau = 0.0;
+    ctrl->dt_last = 0.0;
+    ctrl->vmax_bits[0] = ctrl->vmax_bits[1] = 0ull;
+    ctrl->cmax_bits[0] = ctrl->cmax_bits[1] = 0ull;
+    ctrl->steps = 0;
+    ctrl->err = 0;
+}
+
+// Per-cell speeds |v| and c (Sec. 2.1) of a conserved state.
+template <typename T, int NDIM>
+__device__ __forceinline__ void cell_speeds(T r, T mx, T my, T mz, T e, T gam, T gm1, T &v, T &c)
+{
+    T ux = mx / r;
+    T uy = NDIM >= 2 ? my / r : T(0);
+    T uz = NDIM >= 3 ? mz / r : T(0);
+    v = dsqrt(ux * ux + uy * uy + uz * uz);
+    T p = gm1 * e;
+    c = dsqrt(gam * p / r);
+}
+
+__device__ __forceinline__ void publish_max(Ctrl *ctrl, int slot, double v, double c)
+{
+    v = wave_max(v);
+    c = wave_max(c);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&ctrl->vmax_bits[slot], (unsigned long long)__double_as_longlong(v));
+        atomicMax(&ctrl->cmax_bits[slot], (unsigned long long)__double_as_longlong(c));
+    }
+}
+
+// Maxima of |v| and c over the state into ctrl slot `slot` (first step).
+template <typename T, int NDIM>
+__global__ void k_speeds(const T *__restrict__ U, GridParams gp, Ctrl *ctrl, int slot)
+{
+    const long long N = gp.ncell;
+    const T gam = (T)gp.gamma, gm1 = (T)(gp.gamma - 1.0);
+    double vm = 0.0, cm = 0.0;
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x) {
+        T r = U[c];
+        T mx = U[N + c];
+        T my = NDIM >= 2 ? U[2 * N + c] : T(0);
+        T mz = NDIM >= 3 ? U[3 * N + c] : T(0);
+        T e = U[(2 + NDIM) * N + c];
+        T v, cs;
+        cell_speeds<T, NDIM>(r, mx, my, mz, e, gam, gm1, v, cs);
+        vm = vm > (double)v ? vm : (double)v;
+        cm = cm > (double)cs ? cm : (double)cs;
+    }
+    publish_max(ctrl, slot, vm, cm);
+}
+
+// Deterministic FP64 totals: fixed per-block ranges and fixed tree order.
+constexpr int TOT_THREADS = 256;
+
+template <typename T>
+__global__ __launch_bounds__(TOT_THREADS) void k_totals_partial(const T *__restrict__ U, long long N, int nfs,
+                                                                long long chunk, double *__restrict__ partial)
+{
+    __shared__ double red[TOT_THREADS];
+    long long beg = (long long)blockIdx.x * chunk;
+    long long end = beg + chunk < N ? beg + chunk : N;
+    for (int f = 0; f < nfs; f++) {
+        double s = 0.0;
+        for (long long c = beg + threadIdx.x; c < end; c += TOT_THREADS) s += (double)U[f * N + c];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = TOT_THREADS / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[(long long)blockIdx.x * 6 + f] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(TOT_THREADS) void k_totals_final(const double *__restrict__ partial, int nblocks, int nfs,
+                                                              int ndim, double *__restrict__ out, Ctrl *ctrl,
+                                                              double ncell_for_mean)
+{
+    __shared__ double red[TOT_THREADS];
+    for (int f = 0; f < nfs; f++) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += TOT_THREADS) s += partial[(long long)b * 6 + f];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = TOT_THREADS / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            // stored field f -> ppml_field slot
+            int slot = f == 0 ? 0 : (f <= ndim ? f : (f == ndim + 1 ? 4 : 5));
+            out[slot] = red[0];
+            if (f == 0 && ncell_for_mean > 0.0) ctrl->rho_mean0 = red[0] / ncell_for_mean;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int a = ndim; a < 3; a++) out[1 + a] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Eulerian stage
+// ---------------------------------------------------------------------------
+template <typename T, int NDIM, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void k_euler(const T *__restrict__ U, T *__restrict__ Wst, GridParams gp,
+                                                   Ctrl *ctrl, StepArgs sa, int cz)
+{
+    constexpr int NT = TX * TY;
+    constexpr int HX = GH;
+    constexpr int HY = NDIM >= 2 ? GH : 0;
+    constexpr int PW = TX + 2 * HX;
+    constexpr int PH = TY + 2 * HY;
+    constexpr int PS = PW * PH;
+    constexpr int NXP = (TX + 2) * TY;
+    constexpr int NYP = NDIM >= 2 ? TX * (TY + 2) : 1;
+    constexpr int NXI = (TX + 1) * TY;
+    constexpr int NYI = NDIM >= 2 ? TX * (TY + 1) : 1;
+
+    __shared__ T s_vx[PS];
+    __shared__ T s_vy[NDIM >= 2 ? PS : 1];
+    __shared__ T s_p[PS], s_s[PS], s_r32[PS], s_ps[PS];
+    __shared__ Parab<T> xv[NXP], xp[NXP];
+    __shared__ Parab<T> yv[NYP], yp[NYP];
+    __shared__ VP<T> xi[NXI];
+    __shared__ VP<T> yi[NYI];
+
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int nx = gp.n[0], ny = gp.n[1], nz = gp.n[2];
+    const long long N = gp.ncell;
+
+    const double tau_d = compute_tau(ctrl, gp, sa);
+    const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && tid == 0;
+    if (!(tau_d > 0.0)) {
+        // step is a no-op: carry the maxima of the unchanged state forward
+        if (lead) {
+            ctrl->tau = 0.0;
+            ctrl->vmax_bits[sa.slot ^ 1] = ctrl->vmax_bits[sa.slot];
+            ctrl->cmax_bits[sa.slot ^ 1] = ctrl->cmax_bits[sa.slot];
+        }
+        return;
+    }
+    if (lead) {
+        ctrl->tau = tau_d;
+        ctrl->vmax_bits[sa.slot ^ 1] = 0ull;
+        ctrl->cmax_bits[sa.slot ^ 1] = 0ull;
+    }
+
+    const T gam = (T)gp.gamma;
+    const T gm1 = (T)(gp.gamma - 1.0);
+    const T tau = (T)tau_d;
+    const T hx = (T)gp.h[0], hy = (T)gp.h[1], hz = (T)gp.h[2];
+    const T ihx = (T)gp.inv_h[0], ihy = (T)gp.inv_h[1], ihz = (T)gp.inv_h[2];
+    const T tohx = (T)(tau_d * gp.inv_h[0]), tohy = (T)(tau_d * gp.inv_h[1]), tohz = (T)(tau_d * gp.inv_h[2]);
+    (void)hz;
+    (void)ihz;
+    (void)tohz;
+    (void)hy;
+    (void)ihy;
+    (void)tohy;
+
+    const int gx = x0 + tx, gy = y0 + ty;
+    const bool valid = gx < nx && (NDIM < 2 || gy < ny);
+    int fdum;
+    const int cx_ = map_index(gx, nx, gp.bc_lo[0], gp.bc_hi[0], fdum);
+    const int cy_ = NDIM >= 2 ? map_index(gy, ny, gp.bc_lo[1], gp.bc_hi[1], fdum) : 0;
+
+    int z0 = 0, z1 = 1;
+    if constexpr (NDIM == 3) {
+        z0 = blockIdx.z * cz;
+        z1 = z0 + cz < nz ? z0 + cz : nz;
+    }
+
+    // z pipeline registers (3-D): values of the thread's own column
+    T qv0 = 1, qv1 = 1, qv2 = 1, qp0 = 1, qp1 = 1, qp2 = 1;  // q_{m-2}, q_{m-1}, q_m
+    T dmv = 0, dmp = 0;                                      // slope at m-2
+    T qIv = 1, qIp = 1;                                      // interface value (m-3)+1/2
+    Parab<T> pv_prev = {1, 1, 0}, pp_prev = {1, 1, 0};       // parabola of cell m-3
+    T sr0 = 1, sr1 = 1, sr2 = 1, sr3 = 1;                    // sqrt(rho) at m-3..m
+    T rr0 = 1, rr1 = 1, rr2 = 1, rr3 = 1;                    // rho^{3/2}
+    T pr0 = 1, pr1 = 1, pr2 = 1, pr3 = 1;                    // p sqrt(rho)
+    T Vprev = 0, Pprev = 0;
+
+    const int m_beg = NDIM == 3 ? z0 - 3 : 0;
+    const int m_end = NDIM == 3 ? z1 + 3 : 1;
+    for (int m = m_beg; m < m_end; ++m) {
+        const int k = NDIM == 3 ? m - 3 : 0;
+        T DPz = 0, DPVz = 0, DVz = 0;
+        if constexpr (NDIM == 3) {
+            int fz;
+            const int mz = map_index(m, nz, gp.bc_lo[2], gp.bc_hi[2], fz);
+            const long long c = ((long long)mz * ny + cy_) * nx + cx_;
+            const T rho = U[c];
+            T mzv = U[3 * N + c];
+            if (fz) mzv = -mzv;
+            const T e = U[5 * N + c];
+            const T vz = mzv / rho;
+            const T p = gm1 * e;
+            const T s = dsqrt(rho);
+            qv0 = qv1; qv1 = qv2; qv2 = vz;
+            qp0 = qp1; qp1 = qp2; qp2 = p;
+            sr0 = sr1; sr1 = sr2; sr2 = sr3; sr3 = s;
+            rr0 = rr1; rr1 = rr2; rr2 = rr3; rr3 = rho * s;
+            pr0 = pr1; pr1 = pr2; pr2 = pr3; pr3 = p * s;
+            const T dv_new = limited_slope(qv0, qv1, qv2);
+            const T dp_new = limited_slope(qp0, qp1, qp2);
+            const T qIv_new = interface_value(qv0, qv1, dmv, dv_new);
+            const T qIp_new = interface_value(qp0, qp1, dmp, dp_new);
+            const Parab<T> pv_new = monotonize(qv0, qIv, qIv_new);
+            const Parab<T> pp_new = monotonize(qp0, qIp, qIp_new);
+            dmv = dv_new; dmp = dp_new; qIv = qIv_new; qIp = qIp_new;
+            // interface between planes m-3 and m-2
+            const VP<T> vpz = riemann(sr0, sr1, rr0, rr1, pr0, pr1, pv_prev, pv_new, pp_prev, pp_new, gam, tau, hz,
+                                      tohz);
+            DPz = PPML_DIV(vpz.P - Pprev, hz, ihz);
+            DPVz = PPML_DIV(vpz.P * vpz.V - Pprev * Vprev, hz, ihz);
+            DVz = PPML_DIV(vpz.V - Vprev, hz, ihz);
+            Vprev = vpz.V;
+            Pprev = vpz.P;
+            pv_prev = pv_new;
+            pp_prev = pp_new;
+            if (k < z0) continue;  // warm-up planes: uniform over the block
+        }
+
+        // ---- x / y directions of plane k from LDS ----
+        for (int li = tid; li < PS; li += NT) {
+            const int ix = li % PW, iy = li / PW;
+            const int dx = ix - HX, dy = iy - HY;
+            const bool cross = (dy >= 0 && dy < TY) || (dx >= 0 && dx < TX);
+            if (!cross) continue;
+            int fx, fy = 0;
+            const int ax = map_index(x0 + dx, nx, gp.bc_lo[0], gp.bc_hi[0], fx);
+            const int ay = NDIM >= 2 ? map_index(y0 + dy, ny, gp.bc_lo[1], gp.bc_hi[1], fy) : 0;
+            const long long c = ((long long)k * ny + ay) * nx + ax;
+            const T rho = U[c];
+            T mxv = U[N + c];
+            if (fx) mxv = -mxv;
+            const T e = U[(2 + NDIM) * N + c];
+#ifdef PPML_EXACT
+            s_vx[li] = mxv / rho;
+#else
+            const T ir = T(1) / rho;
+            s_vx[li] = mxv * ir;
+#endif
+            if constexpr (NDIM >= 2) {
+                T myv = U[2 * N + c];
+                if (fy) myv = -myv;
+#ifdef PPML_EXACT
+                s_vy[li] = myv / rho;
+#else
+                s_vy[li] = myv * ir;
+#endif
+            }
+            const T p = gm1 * e;
+            const T s = dsqrt(rho);
+            s_p[li] = p;
+            s_s[li] = s;
+            s_r32[li] = rho * s;
+            s_ps[li] = p * s;
+        }
+        __syncthreads();
+        for (int j = tid; j < NXP; j += NT) {
+            const int cx = j % (TX + 2), cy = j / (TX + 2);
+            const int li = (cy + HY) * PW + cx + 2;
+            xv[j] = parabola5(s_vx[li - 2], s_vx[li - 1], s_vx[li], s_vx[li + 1], s_vx[li + 2]);
+            xp[j] = parabola5(s_p[li - 2], s_p[li - 1], s_p[li], s_p[li + 1], s_p[li + 2]);
+        }
+        if constexpr (NDIM >= 2) {
+            for (int j = tid; j < NYP; j += NT) {
+                const int cx = j % TX, cy = j / TX;
+                const int li = (cy - 1 + HY) * PW + cx + HX;
+                yv[j] = parabola5(s_vy[li - 2 * PW], s_vy[li - PW], s_vy[li], s_vy[li + PW], s_vy[li + 2 * PW]);
+                yp[j] = parabola5(s_p[li - 2 * PW], s_p[li - PW], s_p[li], s_p[li + PW], s_p[li + 2 * PW]);
+            }
+        }
+        __syncthreads();
+        for (int j = tid; j < NXI; j += NT) {
+            const int ix = j % (TX + 1), cy = j / (TX + 1);
+            const int la = (cy + HY) * PW + ix - 1 + HX, lb = la + 1;
+            const int pa = cy * (TX + 2) + ix, pb = pa + 1;
+            xi[j] = riemann(s_s[la], s_s[lb], s_r32[la], s_r32[lb], s_ps[la], s_ps[lb], xv[pa], xv[pb], xp[pa], xp[pb],
+                            gam, tau, hx, tohx);
+        }
+        if constexpr (NDIM >= 2) {
+            for (int j = tid; j < NYI; j += NT) {
+                const int cx = j % TX, iy = j / TX;
+                const int la = (iy - 1 + HY) * PW + cx + HX, lb = la + PW;
+                const int pa = iy * TX + cx, pb = pa + TX;
+                yi[j] = riemann(s_s[la], s_s[lb], s_r32[la], s_r32[lb], s_ps[la], s_ps[lb], yv[pa], yv[pb], yp[pa],
+                                yp[pb], gam, tau, hy, tohy);
+            }
+        }
+        __syncthreads();
+
+        if (valid) {
+            const VP<T> a = xi[ty * (TX + 1) + tx], b = xi[ty * (TX + 1) + tx + 1];
+            const T DPx = PPML_DIV(b.P - a.P, hx, ihx);
+            T sPV = PPML_DIV(b.P * b.V - a.P * a.V, hx, ihx);
+            T sV = PPML_DIV(b.V - a.V, hx, ihx);
+            T DPy = 0;
+            if constexpr (NDIM >= 2) {
+                const VP<T> c0 = yi[ty * TX + tx], c1 = yi[(ty + 1) * TX + tx];
+                DPy = PPML_DIV(c1.P - c0.P, hy, ihy);
+                sPV = sPV + PPML_DIV(c1.P * c1.V - c0.P * c0.V, hy, ihy);
+                sV = sV + PPML_DIV(c1.V - c0.V, hy, ihy);
+            }
+            if constexpr (NDIM == 3) {
+                sPV = sPV + DPVz;
+                sV = sV + DVz;
+            }
+            const long long c = ((long long)k * ny + gy) * nx + gx;
+            const T rho = U[c];
+            T mom[3];
+            mom[0] = U[N + c];
+            mom[1] = NDIM >= 2 ? U[2 * N + c] : T(0);
+            mom[2] = NDIM >= 3 ? U[3 * N + c] : T(0);
+            const T Et = U[(1 + NDIM) * N + c];
+            const T e = U[(2 + NDIM) * N + c];
+            T mn[3];
+            mn[0] = mom[0] - tau * DPx;
+            mn[1] = mom[1] - tau * DPy;
+            mn[2] = mom[2] - tau * DPz;
+            T Etn = Et - tau * sPV;
+            T en = e - ((tau * gm1) * e) * sV;
+            if (gp.potential != POT_NONE) {
+                double g[3];
+                potential_grad(gp, gx, gy, k, g);
+                const double work = (double)mom[0] * g[0] + (double)mom[1] * g[1] + (double)mom[2] * g[2];
+                const double tr = tau_d * (double)rho;
+                for (int ax = 0; ax < NDIM; ax++) mn[ax] = (T)((double)mn[ax] - tr * g[ax]);
+                Etn = (T)((double)Etn - tau_d * work);
+            }
+            Wst[c] = rho;
+            Wst[N + c] = mn[0];
+            if constexpr (NDIM >= 2) Wst[2 * N + c] = mn[1];
+            if constexpr (NDIM >= 3) Wst[3 * N + c] = mn[2];
+            Wst[(1 + NDIM) * N + c] = Etn;
+            Wst[(2 + NDIM) * N + c] = en;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Lagrangian stage + energy correction + CFL maxima
+// ---------------------------------------------------------------------------
+// Transverse template of the interface velocity (Sec. 2.3): weights 1/16
+// (corners), 1/8 (edges), 1/4 (centre) in 3-D, (1/4, 1/2, 1/4) in 2-D.
+template <typename T>
+__device__ __forceinline__ T tmpl9(T c11, T c1m, T cm1, T cmm, T e1a, T ema, T e1b, T emb, T ctr)
+{
+    T corners = c11 + c1m + cm1 + cmm;
+    T edges = e1a + ema + e1b + emb;
+    return T(0.0625) * corners + T(0.125) * edges + T(0.25) * ctr;
+}
+template <typename T> __device__ __forceinline__ T tmpl3(T vp, T vm, T ctr)
+{
+    return T(0.25) * (vp + vm) + T(0.5) * ctr;
+}
+
+template <typename T, int NDIM, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void k_lagr(const T *__restrict__ Wst, T *__restrict__ U, GridParams gp,
+                                                  Ctrl *ctrl, StepArgs sa, int cz)
+{
+    constexpr int NT = TX * TY;
+    constexpr int NF = 3 + NDIM;
+    constexpr int HX = GH;
+    constexpr int HY = NDIM >= 2 ? GH : 0;
+    constexpr int PW = TX + 2 * HX;
+    constexpr int PH = TY + 2 * HY;
+    constexpr int PS = PW * PH;
+    constexpr int NXP = (TX + 2) * TY;
+    constexpr int NYP = NDIM >= 2 ? TX * (TY + 2) : 1;
+    constexpr int NXI = (TX + 1) * TY;
+    constexpr int NYI = NDIM >= 2 ? TX * (TY + 1) : 1;
+    constexpr int VW = TX + 2;
+    constexpr int VH = NDIM >= 2 ? TY + 2 : 1;
+    constexpr int VS = VW * VH;
+    constexpr int NR = NDIM == 3 ? 3 : 1;
+
+    __shared__ T s_f[PS];
+    __shared__ T s_sq[PS];
+    __shared__ Parab<T> xq[NXP];
+    __shared__ Parab<T> yq[NYP];
+    __shared__ T xF[NXI], xvh[NXI];
+    __shared__ T yF[NYI], yvh[NYI];
+    __shared__ T s_vx[NR][VS];
+    __shared__ T s_vy[NDIM >= 2 ? NR : 1][NDIM >= 2 ? VS : 1];
+    __shared__ T s_vz[NDIM == 3 ? NR : 1][NDIM == 3 ? VS : 1];
+
+    const double tau_d = ctrl->tau;
+    if (!(tau_d > 0.0)) return;
+    const int tid = threadIdx.x;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && tid == 0) {
+        ctrl->t = ctrl->t + tau_d;
+        ctrl->dt_last = tau_d;
+        ctrl->steps = ctrl->steps + 1;
+    }
+    const int tx = tid % TX, ty = tid / TX;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int nx = gp.n[0], ny = gp.n[1], nz = gp.n[2];
+    const long long N = gp.ncell;
+    const T gam = (T)gp.gamma;
+    const T gm1 = (T)(gp.gamma - 1.0);
+    const T tau = (T)tau_d;
+    const T hx = (T)gp.h[0], hy = (T)gp.h[1], hz = (T)gp.h[2];
+    const T ihx = (T)gp.inv_h[0], ihy = (T)gp.inv_h[1], ihz = (T)gp.inv_h[2];
+    const T tohx = (T)(tau_d * gp.inv_h[0]), tohy = (T)(tau_d * gp.inv_h[1]), tohz = (T)(tau_d * gp.inv_h[2]);
+    (void)hy; (void)ihy; (void)tohy; (void)hz; (void)ihz; (void)tohz; (void)tohx;
+    const double thr = gp.vacuum_ratio * ctrl->rho_mean0;
+
+    const int gx = x0 + tx, gy = y0 + ty;
+    const bool valid = gx < nx && (NDIM < 2 || gy < ny);
+    int fdum;
+    const int cx_ = map_index(gx, nx, gp.bc_lo[0], gp.bc_hi[0], fdum);
+    const int cy_ = NDIM >= 2 ? map_index(gy, ny, gp.bc_lo[1], gp.bc_hi[1], fdum) : 0;
+
+    int z0 = 0, z1 = 1;
+    if constexpr (NDIM == 3) {
+        z0 = blockIdx.z * cz;
+        z1 = z0 + cz < nz ? z0 + cz : nz;
+    }
+
+    // z pipeline registers (3-D), one set per field
+    T q0[NF], q1[NF], q2[NF], dmq[NF], qI[NF], Fzp[NF];
+    Parab<T> pprev[NF];
+#pragma unroll
+    for (int f = 0; f < NF; f++) {
+        q0[f] = q1[f] = q2[f] = T(1);
+        dmq[f] = T(0);
+        qI[f] = T(1);
+        Fzp[f] = T(0);
+        pprev[f] = Parab<T>{T(1), T(1), T(0)};
+    }
+    T sz0 = 1, sz1 = 1, sz2 = 1, sz3 = 1;  // sqrt(rho) of the column at m-3..m
+    T vtz_prev = 0;                        // transverse velocity of the column at m-3
+    double vmax = 0.0, cmax = 0.0;
+
+    const int m_beg = NDIM == 3 ? z0 - 3 : 0;
+    const int m_end = NDIM == 3 ? z1 + 3 : 1;
+    for (int m = m_beg; m < m_end; ++m) {
+        const int k = NDIM == 3 ? m - 3 : 0;
+        T DFz[NF];
+#pragma unroll
+        for (int f = 0; f < NF; f++) DFz[f] = T(0);
+
+        // velocity plane needed by this iteration (3-D: plane m-2; else plane 0)
+        const int vpl = NDIM == 3 ? m - 2 : 0;
+        const int slot = NDIM == 3 ? ((vpl % 3) + 3) % 3 : 0;
+        const bool need_vel = NDIM == 3 ? (m >= z0 + 1) : true;
+        if (need_vel) {
+            int fz = 0;
+            const int az = NDIM == 3 ? map_index(vpl, nz, gp.bc_lo[2], gp.bc_hi[2], fz) : 0;
+            for (int li = tid; li < VS; li += NT) {
+                const int ix = li % VW, iy = li / VW;
+                int fx, fy = 0;
+                const int ax = map_index(x0 + ix - 1, nx, gp.bc_lo[0], gp.bc_hi[0], fx);
+                const int ay = NDIM >= 2 ? map_index(y0 + iy - 1, ny, gp.bc_lo[1], gp.bc_hi[1], fy) : 0;
+                const long long c = ((long long)az * ny + ay) * nx + ax;
+                const T rho = Wst[c];
+                T mxv = Wst[N + c];
+                if (fx) mxv = -mxv;
+#ifdef PPML_EXACT
+                s_vx[slot][li] = mxv / rho;
+#else
+                const T ir = T(1) / rho;
+                s_vx[slot][li] = mxv * ir;
+#endif
+                if constexpr (NDIM >= 2) {
+                    T myv = Wst[2 * N + c];
+                    if (fy) myv = -myv;
+#ifdef PPML_EXACT
+                    s_vy[slot][li] = myv / rho;
+#else
+                    s_vy[slot][li] = myv * ir;
+#endif
+                }
+                if constexpr (NDIM == 3) {
+                    T mzv = Wst[3 * N + c];
+                    if (fz) mzv = -mzv;
+#ifdef PPML_EXACT
+                    s_vz[slot][li] = mzv / rho;
+#else
+                    s_vz[slot][li] = mzv * ir;
+#endif
+                }
+            }
+        }
+
+        if constexpr (NDIM == 3) {
+            // own-column loads of plane m for every field: z parabola of cell m-2
+            int fz;
+            const int mz = map_index(m, nz, gp.bc_lo[2], gp.bc_hi[2], fz);
+            const long long c = ((long long)mz * ny + cy_) * nx + cx_;
+            Parab<T> pnew[NF];
+#pragma unroll
+            for (int f = 0; f < NF; f++) {
+                T v = Wst[f * N + c];
+                if (f == 3 && fz) v = -v;
+                q0[f] = q1[f];
+                q1[f] = q2[f];
+                q2[f] = v;
+                const T dnew = limited_slope(q0[f], q1[f], q2[f]);
+                const T qInew = interface_value(q0[f], q1[f], dmq[f], dnew);
+                pnew[f] = monotonize(q0[f], qI[f], qInew);
+                dmq[f] = dnew;
+                qI[f] = qInew;
+            }
+            sz0 = sz1; sz1 = sz2; sz2 = sz3; sz3 = dsqrt(q2[0]);
+            if (need_vel) {
+                __syncthreads();
+                // transverse velocity of the own column at plane m-2
+                const T *V = s_vz[slot];
+                const int l = (ty + 1) * VW + tx + 1;
+                const T vt = tmpl9(V[l + 1 + VW], V[l + 1 - VW], V[l - 1 + VW], V[l - 1 - VW], V[l + 1], V[l - 1],
+                                   V[l + VW], V[l - VW], V[l]);
+                // interface between planes m-3 and m-2
+                const T vh = interface_velocity(vtz_prev, sz0, vt, sz1);
+#ifdef PPML_EXACT
+                const T z = dabs(vh) * tau / hz;
+#else
+                const T z = dabs(vh) * tohz;
+#endif
+#pragma unroll
+                for (int f = 0; f < NF; f++) {
+                    const T F = upwind_flux(vh, z, pprev[f], pnew[f]);
+                    DFz[f] = PPML_DIV(F - Fzp[f], hz, ihz);
+                    Fzp[f] = F;
+                }
+                vtz_prev = vt;
+            }
+#pragma unroll
+            for (int f = 0; f < NF; f++) pprev[f] = pnew[f];
+            if (k < z0) continue;  // warm-up: uniform over the block
+        } else {
+            __syncthreads();
+        }
+
+        // ---- x / y directions of plane k ----
+        T acc[NF];
+        for (int f = 0; f < NF; f++) {
+            // cross tile of field f (and sqrt(rho) with the first field)
+            for (int li = tid; li < PS; li += NT) {
+                const int ix = li % PW, iy = li / PW;
+                const int dx = ix - HX, dy = iy - HY;
+                const bool cross = (dy >= 0 && dy < TY) || (dx >= 0 && dx < TX);
+                if (!cross) continue;
+                int fx, fy = 0;
+                const int ax = map_index(x0 + dx, nx, gp.bc_lo[0], gp.bc_hi[0], fx);
+                const int ay = NDIM >= 2 ? map_index(y0 + dy, ny, gp.bc_lo[1], gp.bc_hi[1], fy) : 0;
+                const long long c = ((long long)k * ny + ay) * nx + ax;
+                T v = Wst[f * N + c];
+                if ((f == 1 && fx) || (NDIM >= 2 && f == 2 && fy)) v = -v;
+                s_f[li] = v;
+                if (f == 0) s_sq[li] = dsqrt(v);
+            }
+            __syncthreads();
+            if (f == 0) {
+                // interface velocities of the x and y interfaces of the plane
+                const int sm = NDIM == 3 ? ((k - 1) % 3 + 3) % 3 : 0;
+                const int s0 = NDIM == 3 ? (k % 3 + 3) % 3 : 0;
+                const int sp = NDIM == 3 ? ((k + 1) % 3 + 3) % 3 : 0;
+                for (int j = tid; j < NXI; j += NT) {
+                    const int ix = j % (TX + 1), cy = j / (TX + 1);
+                    T vt[2];
+#pragma unroll
+                    for (int u = 0; u < 2; u++) {
+                        const int l = (cy + 1) * VW + ix + u;  // tile-rel x = ix-1+u
+                        if constexpr (NDIM == 3) {
+                            const T *A = s_vx[sm], *B = s_vx[s0], *C = s_vx[sp];
+                            // transverse axes y (first) and z (second)
+                            vt[u] = tmpl9(C[l + VW], A[l + VW], C[l - VW], A[l - VW], B[l + VW], B[l - VW], C[l], A[l],
+                                          B[l]);
+                        } else if constexpr (NDIM == 2) {
+                            const T *B = s_vx[0];
+                            vt[u] = tmpl3(B[l + VW], B[l - VW], B[l]);
+                        } else {
+                            vt[u] = s_vx[0][ix + u];
+                        }
+                    }
+                    const int la = (cy + HY) * PW + ix - 1 + HX;
+                    xvh[j] = interface_velocity(vt[0], s_sq[la], vt[1], s_sq[la + 1]);
+                }
+                if constexpr (NDIM >= 2) {
+                    for (int j = tid; j < NYI; j += NT) {
+                        const int cx = j % TX, iy = j / TX;
+                        T vt[2];
+#pragma unroll
+                        for (int u = 0; u < 2; u++) {
+                            const int l = (iy + u) * VW + cx + 1;  // tile-rel y = iy-1+u
+                            if constexpr (NDIM == 3) {
+                                const T *A = s_vy[sm], *B = s_vy[s0], *C = s_vy[sp];
+                                // transverse axes x (first) and z (second)
+                                vt[u] = tmpl9(C[l + 1], A[l + 1], C[l - 1], A[l - 1], B[l + 1], B[l - 1], C[l], A[l],
+                                              B[l]);
+                            } else {
+                                const T *B = s_vy[0];
+                                vt[u] = tmpl3(B[l + 1], B[l - 1], B[l]);
+                            }
+                        }
+                        const int la = (iy - 1 + HY) * PW + cx + HX;
+                        yvh[j] = interface_velocity(vt[0], s_sq[la], vt[1], s_sq[la + PW]);
+                    }
+                }
+            }
+            for (int j = tid; j < NXP; j += NT) {
+                const int cx = j % (TX + 2), cy = j / (TX + 2);
+                const int li = (cy + HY) * PW + cx + 2;
+                xq[j] = parabola5(s_f[li - 2], s_f[li - 1], s_f[li], s_f[li + 1], s_f[li + 2]);
+            }
+            if constexpr (NDIM >= 2) {
+                for (int j = tid; j < NYP; j += NT) {
+                    const int cx = j % TX, cy = j / TX;
+                    const int li = (cy - 1 + HY) * PW + cx + HX;
+                    yq[j] = parabola5(s_f[li - 2 * PW], s_f[li - PW], s_f[li], s_f[li + PW], s_f[li + 2 * PW]);
+                }
+            }
+            __syncthreads();
+            for (int j = tid; j < NXI; j += NT) {
+                const int ix = j % (TX + 1), cy = j / (TX + 1);
+                const int pa = cy * (TX + 2) + ix;
+                const T vh = xvh[j];
+#ifdef PPML_EXACT
+                const T z = dabs(vh) * tau / hx;
+#else
+                const T z = dabs(vh) * tohx;
+#endif
+                xF[j] = upwind_flux(vh, z, xq[pa], xq[pa + 1]);
+            }
+            if constexpr (NDIM >= 2) {
+                for (int j = tid; j < NYI; j += NT) {
+                    const int cx = j % TX, iy = j / TX;
+                    const int pa = iy * TX + cx;
+                    const T vh = yvh[j];
+#ifdef PPML_EXACT
+                    const T z = dabs(vh) * tau / hy;
+#else
+                    const T z = dabs(vh) * tohy;
+#endif
+                    yF[j] = upwind_flux(vh, z, yq[pa], yq[pa + TX]);
+                }
+            }
+            __syncthreads();
+            T a = PPML_DIV(xF[ty * (TX + 1) + tx + 1] - xF[ty * (TX + 1) + tx], hx, ihx);
+            if constexpr (NDIM >= 2) a = a + PPML_DIV(yF[(ty + 1) * TX + tx] - yF[ty * TX + tx], hy, ihy);
+            if constexpr (NDIM == 3) a = a + DFz[f];
+            acc[f] = a;
+        }
+
+        if (valid) {
+            const long long c = ((long long)k * ny + gy) * nx + gx;
+            T fn[NF];
+#pragma unroll
+            for (int f = 0; f < NF; f++) fn[f] = Wst[f * N + c] - tau * acc[f];
+            // total-energy correction (Sec. 2.4), FP64 arithmetic
+            const double r = (double)fn[0];
+            double mx = (double)fn[1];
+            double my = NDIM >= 2 ? (double)fn[2] : 0.0;
+            double mz = NDIM >= 3 ? (double)fn[3] : 0.0;
+            const double Et = (double)fn[NDIM + 1];
+            double e = (double)fn[NDIM + 2];
+            if (r < thr) {
+                const double E = Et / r, eps = e / r;
+                const double w = __builtin_sqrt(mx * mx + my * my + mz * mz) / r;
+                if (E > eps && w > 0.0) {
+                    const double sc = __builtin_sqrt(2.0 * (E - eps)) / w;
+                    fn[1] = (T)(mx * sc);
+                    if constexpr (NDIM >= 2) fn[2] = (T)(my * sc);
+                    if constexpr (NDIM >= 3) fn[3] = (T)(mz * sc);
+                } else {
+                    fn[1] = T(0);
+                    if constexpr (NDIM >= 2) fn[2] = T(0);
+                    if constexpr (NDIM >= 3) fn[3] = T(0);
+                    fn[NDIM + 2] = (T)Et;
+                }
+            } else {
+                const double kin = (mx * mx + my * my + mz * mz) / (2.0 * r);
+                const double d = Et - kin;
+                if (d > 0.0) fn[NDIM + 2] = (T)d;
+            }
+#pragma unroll
+            for (int f = 0; f < NF; f++) U[f * N + c] = fn[f];
+            T v, cs;
+            cell_speeds<T, NDIM>(fn[0], fn[1], NDIM >= 2 ? fn[2] : T(0), NDIM >= 3 ? fn[3] : T(0), fn[NDIM + 2], gam,
+                                 gm1, v, cs);
+            const bool bad = !(fn[0] > T(0)) || !(fn[NDIM + 2] > T(0)) || !(v == v) || !(cs == cs) ||
+                             __builtin_isinf((double)v) || __builtin_isinf((double)fn[NDIM + 1]);
+            if (bad) atomicOr(&ctrl->err, 1);
+            vmax = vmax > (double)v ? vmax : (double)v;
+            cmax = cmax > (double)cs ? cmax : (double)cs;
+        }
+    }
+    publish_max(ctrl, sa.slot ^ 1, vmax, cmax);
+}
+
+}  // namespace ppml

@@ -1,0 +1,105 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and
+exports every function the header declares, and descriptor validation
+rejects bad input before any device call."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ppml.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ppml_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1607_01105_amd import ppml
+
+    if not os.path.exists(ppml.LIB_PATH):
+        from paper_1607_01105_amd import build
+
+        build.build()
+    return ppml.load()
+
+
+def test_header_lists_expected_api():
+    names = declared_functions()
+    for n in ("ppml_create", "ppml_set_primitive", "ppml_step", "ppml_get_conserved", "ppml_totals", "ppml_destroy"):
+        assert n in names
+
+
+@pytest.mark.parametrize("path_attr", ["LIB_PATH", "LIB_EXACT_PATH"])
+def test_library_exports_every_declared_symbol(path_attr):
+    from paper_1607_01105_amd import ppml
+
+    path = getattr(ppml, path_attr)
+    if not os.path.exists(path):
+        from paper_1607_01105_amd import build
+
+        build.build()
+    lib = ppml.load(path)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(ppml.EXPORTS)
+
+
+def test_version_and_strerror(lib):
+    assert lib.ppml_version() >= 100
+    assert lib.ppml_strerror(0) == b"ok"
+    assert lib.ppml_strerror(-4).startswith(b"non-physical")
+
+
+def _desc(**kw):
+    from paper_1607_01105_amd import ppml
+
+    base = dict(ndim=3, n=(16, 8, 4), lo=(0, 0, 0), hi=(1, 1, 1), gamma=1.4, cfl=0.3)
+    base.update(kw)
+    return ppml.make_desc(**base)
+
+
+def test_state_and_scratch_bytes(lib):
+    from paper_1607_01105_amd import ppml
+
+    d = _desc(prec="fp32")
+    assert ppml.ppml_state_bytes(d, lib) == 6 * 16 * 8 * 4 * 4
+    d = _desc(prec="fp64", ndim=2, n=(10, 7))
+    assert ppml.ppml_state_bytes(d, lib) == 5 * 70 * 8
+    assert ppml.ppml_scratch_bytes(d, lib) >= ppml.ppml_state_bytes(d, lib)
+
+
+@pytest.mark.parametrize("bad", [dict(ndim=4), dict(gamma=1.0), dict(cfl=1.0), dict(cfl=0.0),
+                                 dict(n=(0, 8, 4)), dict(hi=(0, 1, 1)), dict(bc="reflect", n=(2, 8, 4)),
+                                 dict(vacuum_ratio=-1.0)])
+def test_invalid_descriptors_rejected(lib, bad):
+    from paper_1607_01105_amd import ppml
+
+    d = _desc(**bad)
+    assert ppml.ppml_state_bytes(d, lib) == 0
+    assert len(lib.ppml_last_error()) > 0
+    h = C.c_void_p()
+    rc = lib.ppml_create(C.byref(d), C.c_void_p(256), C.c_void_p(512), None, C.byref(h))
+    assert rc == ppml.PPML_EINVAL
+
+
+def test_create_rejects_null_and_misaligned(lib):
+    from paper_1607_01105_amd import ppml
+
+    d = _desc()
+    h = C.c_void_p()
+    assert lib.ppml_create(C.byref(d), None, C.c_void_p(512), None, C.byref(h)) == ppml.PPML_EINVAL
+    assert lib.ppml_create(C.byref(d), C.c_void_p(260), C.c_void_p(512), None, C.byref(h)) == ppml.PPML_EINVAL
+
+
+def test_null_grid_rejected(lib):
+    from paper_1607_01105_amd import ppml
+
+    assert lib.ppml_step(None, 1, 0.0, 0.0) == ppml.PPML_EINVAL
+    assert lib.ppml_destroy(None) == ppml.PPML_EINVAL
