@@ -37,6 +37,44 @@ WORKLOAD = ("3D 256^3 periodic unit cube, gamma 5/3, rho = 1 + 0.1 * 8 random mo
             "p = 1 with p = 100 sphere r = 0.1 at centre, u = 0, CFL 0.3, 100 steps")
 
 
+# Algorithmic floating-point operations per zone of each 3-D stage kernel,
+# counted from the method (each add, sub, mul, div and sqrt of the formulas is
+# one operation; interface quantities shared by two cells counted once;
+# compares, min/max and selects not counted).  Eulerian: cell prep 7 +
+# 3 axes x (2 parabolas 58 + Riemann 48 + differences 7) + update 16 = 362.
+# Lagrangian: 3 axes x (velocity 1 + 9-point template 11 + interface velocity
+# 5 + Courant number 2 + 6 fields x (parabola 29 + average 5 + flux 3) +
+# shared average terms 4) + sqrt(rho) 1 + update 24 + energy correction 8 +
+# CFL speeds 13 = 781.  Parabola 29 = limited slope 7 + interface value 5 +
+# monotonisation 17.
+ALGO_FLOP_PER_ZONE_3D = {"euler": 362, "lagr": 781}
+# VALU peak of the kernels as built (packed FP32 instructions are disabled):
+# 256 CU x 64 lanes x 2 FLOP (FMA) x 2.4 GHz = 78.6 TFLOP/s for FP32 and for
+# FP64; the published FP32 figure (157.3) assumes packed FP32.
+VALU_PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_box256.json")
+KERNEL_SOURCES = ("paper_1607_01105_amd/csrc/ppml_kernels.hpp", "paper_1607_01105_amd/csrc/ppml_device.hpp",
+                  "paper_1607_01105_amd/build.py")
+
+
+def measured_traffic(kernel_key: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by the calibration kernel), or None when
+    the kernel sources changed since the counters were taken."""
+    import hashlib
+
+    try:
+        tr = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, s), "rb").read())
+    if tr.get("source_sha256") != h.hexdigest() or kernel_key not in tr:
+        return None
+    return tr[kernel_key]["bytes"]
+
+
 def algorithmic_bytes_per_zone(kernel: str, ndim: int, width: int) -> int:
     """Compulsory HBM bytes of one kernel per zone: the Eulerian kernel reads
     the F = 3 + ndim conserved fields and writes the F - 1 it changes (rho is
@@ -101,6 +139,9 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run one plain 256 MiB streaming kernel (torch.mul out-of-place: reads 256 MiB, "
+                         "writes 256 MiB), the reference kernel for scaling the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
@@ -112,6 +153,14 @@ def main():
     from paper_1607_01105_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        torch.mul(a, 2.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
+        print("[bench] calibration copy: 268435456 bytes read, 268435456 bytes written", file=sys.stderr, flush=True)
     prob = W.periodic_modes(args.n, seed=0)
     cells = prob.cells
     res = {}
@@ -129,11 +178,17 @@ def main():
     r = res[head]
     value = cells * args.steps / (r["ms"] * 1e-3)
     width = 4 if head == "fp32" else 8
-    # dominant kernel and its HBM roofline
+    # dominant kernel; the path is bound by the vector ALUs (see the design
+    # notes): algorithmic FLOPs per launch / measured launch duration
     kern = "lagr" if r["ms_lagr"] >= r["ms_euler"] else "euler"
     ms_k = r["ms_" + kern]
+    dt = "f32" if head == "fp32" else "f64"
+    flops_launch = ALGO_FLOP_PER_ZONE_3D[kern] * cells
+    achieved_tflops = flops_launch / (ms_k * 1e-3) / 1e12
     bytes_launch = algorithmic_bytes_per_zone(kern, 3, width) * cells
-    achieved = bytes_launch / (ms_k * 1e-3) / 1e9
+    achieved_gbs = bytes_launch / (ms_k * 1e-3) / 1e9
+    key = f"k_{kern}<{'float' if width == 4 else 'double'},3,32,8" + (f",{6 if width == 4 else 3}>" if kern == "lagr" else ">")
+    traffic = measured_traffic(key)
     out = {
         "metric": "zone-updates/sec FP32 vs FP64 at stated L1 error; p50/p99 latency when served",
         "value": value,
@@ -150,9 +205,14 @@ def main():
         "config": {"workload": WORKLOAD, "grid": [args.n] * 3, "gamma": 5.0 / 3.0, "cfl": 0.3, "seed": 0,
                    "state": head},
         "kernels_ms": {"euler": r["ms_euler"], "lagr": r["ms_lagr"]},
-        "roofline": {"bound": "hbm", "kernel": "k_" + kern, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_zone": algorithmic_bytes_per_zone(kern, 3, width)},
+        "roofline": {"bound": "alu", "kernel": "k_" + kern, "achieved": achieved_tflops,
+                     "peak": VALU_PEAK_TFLOPS[dt], "unit": "TFLOP/s", "frac": achieved_tflops / VALU_PEAK_TFLOPS[dt],
+                     "traffic": traffic, "algorithmic_flop_per_zone": ALGO_FLOP_PER_ZONE_3D[kern],
+                     "launch_ms": ms_k, "published_peak": FP32_VECTOR_PEAK_TFLOPS if dt == "f32" else FP64_VECTOR_PEAK_TFLOPS,
+                     "hbm": {"achieved_GBs": achieved_gbs, "peak_GBs": HBM_PEAK_GBS,
+                             "frac": achieved_gbs / HBM_PEAK_GBS,
+                             "algorithmic_bytes_per_zone": algorithmic_bytes_per_zone(kern, 3, width),
+                             "measured_GBs": (traffic / (ms_k * 1e-3) / 1e9) if traffic else None}},
     }
     if "fp64" in res and "fp32" in res:
         import numpy as np

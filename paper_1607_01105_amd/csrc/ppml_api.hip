@@ -40,6 +40,12 @@ constexpr int T1X = 256;
 constexpr int T2X = 32, T2Y = 8;
 constexpr int T3X = 32, T3Y = 8;
 
+// Fields per LDS pass of the Lagrangian kernel (all six in FP32; FP64 in
+// two passes to keep two work groups per CU).
+template <typename T> struct LG {
+    static constexpr int g = sizeof(T) == 4 ? 6 : 3;
+};
+
 int nfields(const ppml_desc *d) { return 3 + d->ndim; }
 
 size_t elem(const ppml_desc *d) { return d->prec == PPML_FP64 ? sizeof(double) : sizeof(float); }
@@ -120,7 +126,6 @@ struct ppml_grid {
     double *totals;
     long long step_count;  // steps enqueued (selects the CFL slot)
     bool has_state;
-    int cz;                // z chunk of the 3-D kernels
     std::vector<hipEvent_t> ev;  // 3 events per timed step
     long long timed;             // steps recorded since the last read
 };
@@ -141,42 +146,24 @@ template <typename T> void launch_speeds(ppml_grid *g, int slot)
 template <typename T> void launch_step(ppml_grid *g, const StepArgs &sa, hipEvent_t *ev)
 {
     // ev (may be NULL): events recorded before, between and after the kernels
-#define PPML_MARK(i)                                                                                   \
-    if (ev) (void)hipEventRecord(ev[i], g->stream)
     const T *U = (const T *)g->state;
     T *Us = (T *)g->state;
     T *W = (T *)g->half;
     const GridParams &gp = g->gp;
+    const int nb = gp.tiles[0] * gp.tiles[1] * gp.tiles[2];
+    if (ev) (void)hipEventRecord(ev[0], g->stream);
     switch (g->d.ndim) {
-    case 1: {
-        dim3 grid((gp.n[0] + T1X - 1) / T1X, 1, 1);
-        PPML_MARK(0);
-        k_euler<T, 1, T1X, 1><<<grid, T1X, 0, g->stream>>>(U, W, gp, g->ctrl, sa, 1);
-        PPML_MARK(1);
-        k_lagr<T, 1, T1X, 1><<<grid, T1X, 0, g->stream>>>(W, Us, gp, g->ctrl, sa, 1);
-        PPML_MARK(2);
-        break;
+    case 1: k_euler<T, 1, T1X, 1><<<nb, T1X, 0, g->stream>>>(U, W, gp, g->ctrl, sa); break;
+    case 2: k_euler<T, 2, T2X, T2Y><<<nb, T2X * T2Y, 0, g->stream>>>(U, W, gp, g->ctrl, sa); break;
+    default: k_euler<T, 3, T3X, T3Y><<<nb, T3X * T3Y, 0, g->stream>>>(U, W, gp, g->ctrl, sa); break;
     }
-    case 2: {
-        dim3 grid((gp.n[0] + T2X - 1) / T2X, (gp.n[1] + T2Y - 1) / T2Y, 1);
-        PPML_MARK(0);
-        k_euler<T, 2, T2X, T2Y><<<grid, T2X * T2Y, 0, g->stream>>>(U, W, gp, g->ctrl, sa, 1);
-        PPML_MARK(1);
-        k_lagr<T, 2, T2X, T2Y><<<grid, T2X * T2Y, 0, g->stream>>>(W, Us, gp, g->ctrl, sa, 1);
-        PPML_MARK(2);
-        break;
+    if (ev) (void)hipEventRecord(ev[1], g->stream);
+    switch (g->d.ndim) {
+    case 1: k_lagr<T, 1, T1X, 1, LG<T>::g><<<nb, T1X, 0, g->stream>>>(W, Us, gp, g->ctrl, sa); break;
+    case 2: k_lagr<T, 2, T2X, T2Y, LG<T>::g><<<nb, T2X * T2Y, 0, g->stream>>>(W, Us, gp, g->ctrl, sa); break;
+    default: k_lagr<T, 3, T3X, T3Y, LG<T>::g><<<nb, T3X * T3Y, 0, g->stream>>>(W, Us, gp, g->ctrl, sa); break;
     }
-    default: {
-        dim3 grid((gp.n[0] + T3X - 1) / T3X, (gp.n[1] + T3Y - 1) / T3Y, (gp.n[2] + g->cz - 1) / g->cz);
-        PPML_MARK(0);
-        k_euler<T, 3, T3X, T3Y><<<grid, T3X * T3Y, 0, g->stream>>>(U, W, gp, g->ctrl, sa, g->cz);
-        PPML_MARK(1);
-        k_lagr<T, 3, T3X, T3Y><<<grid, T3X * T3Y, 0, g->stream>>>(W, Us, gp, g->ctrl, sa, g->cz);
-        PPML_MARK(2);
-        break;
-    }
-    }
-#undef PPML_MARK
+    if (ev) (void)hipEventRecord(ev[2], g->stream);
 }
 
 template <typename T> void launch_totals(ppml_grid *g, double mean_cells)
@@ -295,14 +282,25 @@ int ppml_create(const ppml_desc *d, void *state_dev, void *scratch_dev, void *hi
     gp.vacuum_ratio = d->vacuum_ratio;
     gp.potential = d->potential;
     for (int i = 0; i < 8; i++) gp.pot[i] = d->pot[i];
-    // z chunk: enough workgroups to fill 256 CUs several times over
-    if (d->ndim == 3) {
-        long long tiles = (long long)((gp.n[0] + T3X - 1) / T3X) * ((gp.n[1] + T3Y - 1) / T3Y);
+    // tiles of the stage kernels; 3-D: z chunk small enough that the launch
+    // has enough work groups to fill 256 CUs several times over
+    if (d->ndim == 1) {
+        gp.tiles[0] = (gp.n[0] + T1X - 1) / T1X;
+        gp.tiles[1] = gp.tiles[2] = 1;
+        gp.cz = 1;
+    } else if (d->ndim == 2) {
+        gp.tiles[0] = (gp.n[0] + T2X - 1) / T2X;
+        gp.tiles[1] = (gp.n[1] + T2Y - 1) / T2Y;
+        gp.tiles[2] = 1;
+        gp.cz = 1;
+    } else {
+        gp.tiles[0] = (gp.n[0] + T3X - 1) / T3X;
+        gp.tiles[1] = (gp.n[1] + T3Y - 1) / T3Y;
+        long long tiles = (long long)gp.tiles[0] * gp.tiles[1];
         int cz = gp.n[2];
         while (cz > 16 && tiles * ((gp.n[2] + cz - 1) / cz) < 2048) cz = (cz + 1) / 2;
-        g->cz = cz;
-    } else {
-        g->cz = 1;
+        gp.cz = cz;
+        gp.tiles[2] = (gp.n[2] + cz - 1) / cz;
     }
     g->has_state = false;
     g->step_count = 0;

@@ -34,6 +34,8 @@ struct GridParams {
     int bc_lo[3], bc_hi[3];
     int potential;
     double pot[8];
+    int tiles[3];  // work-group tiles along x, y and z chunks of the stage kernels
+    int cz;        // planes per z chunk (3-D)
 };
 
 // Device control block of one grid (lives in the scratch area).
@@ -277,6 +279,22 @@ __device__ __forceinline__ double compute_tau(const Ctrl *c, const GridParams &g
         else if (tau > rem) tau = rem;
     }
     return tau;
+}
+
+// Tile of this work group.  Work groups are dispatched round-robin over the
+// 8 XCDs of the chip by their linear id; giving each XCD a contiguous range
+// of tiles (x fastest, then y, then z chunk) keeps the halo planes that
+// neighbouring tiles share in that XCD's L2.
+__device__ __forceinline__ void block_tile(const GridParams &gp, int &bx, int &by, int &bz)
+{
+    const int nb = gp.tiles[0] * gp.tiles[1] * gp.tiles[2];
+    const int b = blockIdx.x;
+    const int x = b & 7, q = nb >> 3, r = nb & 7;
+    const int L = x * q + (x < r ? x : r) + (b >> 3);
+    bx = L % gp.tiles[0];
+    const int t = L / gp.tiles[0];
+    by = t % gp.tiles[1];
+    bz = t / gp.tiles[1];
 }
 
 // Wave-wide maximum (wave64).

@@ -169,7 +169,7 @@ __global__ __launch_bounds__(TOT_THREADS) void k_totals_final(const double *__re
 // ---------------------------------------------------------------------------
 template <typename T, int NDIM, int TX, int TY>
 __global__ __launch_bounds__(TX *TY) void k_euler(const T *__restrict__ U, T *__restrict__ Wst, GridParams gp,
-                                                   Ctrl *ctrl, StepArgs sa, int cz)
+                                                   Ctrl *ctrl, StepArgs sa)
 {
     constexpr int NT = TX * TY;
     constexpr int HX = GH;
@@ -192,12 +192,14 @@ __global__ __launch_bounds__(TX *TY) void k_euler(const T *__restrict__ U, T *__
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    int bx, by, bz;
+    block_tile(gp, bx, by, bz);
+    const int x0 = bx * TX, y0 = by * TY;
     const int nx = gp.n[0], ny = gp.n[1], nz = gp.n[2];
     const long long N = gp.ncell;
 
     const double tau_d = compute_tau(ctrl, gp, sa);
-    const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && tid == 0;
+    const bool lead = blockIdx.x == 0 && tid == 0;
     if (!(tau_d > 0.0)) {
         // step is a no-op: carry the maxima of the unchanged state forward
         if (lead) {
@@ -234,8 +236,8 @@ __global__ __launch_bounds__(TX *TY) void k_euler(const T *__restrict__ U, T *__
 
     int z0 = 0, z1 = 1;
     if constexpr (NDIM == 3) {
-        z0 = blockIdx.z * cz;
-        z1 = z0 + cz < nz ? z0 + cz : nz;
+        z0 = bz * gp.cz;
+        z1 = z0 + gp.cz < nz ? z0 + gp.cz : nz;
     }
 
     // z pipeline registers (3-D): values of the thread's own column
@@ -424,46 +426,57 @@ template <typename T> __device__ __forceinline__ T tmpl3(T vp, T vm, T ctr)
     return T(0.25) * (vp + vm) + T(0.5) * ctr;
 }
 
-template <typename T, int NDIM, int TX, int TY>
+template <typename T, int NDIM, int TX, int TY, int G>
 __global__ __launch_bounds__(TX *TY) void k_lagr(const T *__restrict__ Wst, T *__restrict__ U, GridParams gp,
-                                                  Ctrl *ctrl, StepArgs sa, int cz)
+                                                  Ctrl *ctrl, StepArgs sa)
 {
     constexpr int NT = TX * TY;
     constexpr int NF = 3 + NDIM;
+    constexpr int NPASS = (NF + G - 1) / G;
     constexpr int HX = GH;
     constexpr int HY = NDIM >= 2 ? GH : 0;
     constexpr int PW = TX + 2 * HX;
     constexpr int PH = TY + 2 * HY;
     constexpr int PS = PW * PH;
-    constexpr int NXP = (TX + 2) * TY;
-    constexpr int NYP = NDIM >= 2 ? TX * (TY + 2) : 1;
+    // faces carrying interface values: x faces between tile-rel cells fx-2 and
+    // fx-1 (fx = 0 .. TX+2), y faces between rows fy-2 and fy-1
+    constexpr int NXQ = (TX + 3) * TY;
+    constexpr int NYQ = NDIM >= 2 ? TX * (TY + 3) : 0;
+    // flux interfaces: x between cells i-1 and i (i = 0 .. TX), y likewise
     constexpr int NXI = (TX + 1) * TY;
-    constexpr int NYI = NDIM >= 2 ? TX * (TY + 1) : 1;
+    constexpr int NYI = NDIM >= 2 ? TX * (TY + 1) : 0;
     constexpr int VW = TX + 2;
     constexpr int VH = NDIM >= 2 ? TY + 2 : 1;
     constexpr int VS = VW * VH;
     constexpr int NR = NDIM == 3 ? 3 : 1;
 
-    __shared__ T s_f[PS];
-    __shared__ T s_sq[PS];
-    __shared__ Parab<T> xq[NXP];
-    __shared__ Parab<T> yq[NYP];
-    __shared__ T xF[NXI], xvh[NXI];
-    __shared__ T yF[NYI], yvh[NYI];
+    __shared__ T s_f[G][PS];
+    __shared__ T s_qx[G][NXQ];
+    __shared__ T s_qy[G][NYQ > 0 ? NYQ : 1];
+    // fluxes reuse the interface-value arrays once those are consumed
+    static_assert(NXI <= NXQ && NYI <= NYQ + 1, "flux arrays must fit in the face arrays");
+    T (*s_Fx)[NXQ] = s_qx;
+    T (*s_Fy)[NYQ > 0 ? NYQ : 1] = s_qy;
+    __shared__ T xvh[NXI];
+    __shared__ T yvh[NYI > 0 ? NYI : 1];
     __shared__ T s_vx[NR][VS];
     __shared__ T s_vy[NDIM >= 2 ? NR : 1][NDIM >= 2 ? VS : 1];
-    __shared__ T s_vz[NDIM == 3 ? NR : 1][NDIM == 3 ? VS : 1];
+    // v_z is only needed on the newest plane; two slots alternate so that a
+    // plane's slot is never rewritten while the previous one is being read
+    __shared__ T s_vz[NDIM == 3 ? 2 : 1][NDIM == 3 ? VS : 1];
 
     const double tau_d = ctrl->tau;
     if (!(tau_d > 0.0)) return;
     const int tid = threadIdx.x;
-    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && tid == 0) {
+    if (blockIdx.x == 0 && tid == 0) {
         ctrl->t = ctrl->t + tau_d;
         ctrl->dt_last = tau_d;
         ctrl->steps = ctrl->steps + 1;
     }
     const int tx = tid % TX, ty = tid / TX;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    int bx, by, bz;
+    block_tile(gp, bx, by, bz);
+    const int x0 = bx * TX, y0 = by * TY;
     const int nx = gp.n[0], ny = gp.n[1], nz = gp.n[2];
     const long long N = gp.ncell;
     const T gam = (T)gp.gamma;
@@ -472,7 +485,7 @@ __global__ __launch_bounds__(TX *TY) void k_lagr(const T *__restrict__ Wst, T *_
     const T hx = (T)gp.h[0], hy = (T)gp.h[1], hz = (T)gp.h[2];
     const T ihx = (T)gp.inv_h[0], ihy = (T)gp.inv_h[1], ihz = (T)gp.inv_h[2];
     const T tohx = (T)(tau_d * gp.inv_h[0]), tohy = (T)(tau_d * gp.inv_h[1]), tohz = (T)(tau_d * gp.inv_h[2]);
-    (void)hy; (void)ihy; (void)tohy; (void)hz; (void)ihz; (void)tohz; (void)tohx;
+    (void)hy; (void)ihy; (void)tohy; (void)hz; (void)ihz; (void)tohz; (void)tohx; (void)hx;
     const double thr = gp.vacuum_ratio * ctrl->rho_mean0;
 
     const int gx = x0 + tx, gy = y0 + ty;
@@ -483,8 +496,8 @@ __global__ __launch_bounds__(TX *TY) void k_lagr(const T *__restrict__ Wst, T *_
 
     int z0 = 0, z1 = 1;
     if constexpr (NDIM == 3) {
-        z0 = blockIdx.z * cz;
-        z1 = z0 + cz < nz ? z0 + cz : nz;
+        z0 = bz * gp.cz;
+        z1 = z0 + gp.cz < nz ? z0 + gp.cz : nz;
     }
 
     // z pipeline registers (3-D), one set per field
@@ -513,6 +526,7 @@ __global__ __launch_bounds__(TX *TY) void k_lagr(const T *__restrict__ Wst, T *_
         // velocity plane needed by this iteration (3-D: plane m-2; else plane 0)
         const int vpl = NDIM == 3 ? m - 2 : 0;
         const int slot = NDIM == 3 ? ((vpl % 3) + 3) % 3 : 0;
+        const int zslot = NDIM == 3 ? (vpl & 1) : 0;
         const bool need_vel = NDIM == 3 ? (m >= z0 + 1) : true;
         if (need_vel) {
             int fz = 0;
@@ -545,9 +559,9 @@ __global__ __launch_bounds__(TX *TY) void k_lagr(const T *__restrict__ Wst, T *_
                     T mzv = Wst[3 * N + c];
                     if (fz) mzv = -mzv;
 #ifdef PPML_EXACT
-                    s_vz[slot][li] = mzv / rho;
+                    s_vz[zslot][li] = mzv / rho;
 #else
-                    s_vz[slot][li] = mzv * ir;
+                    s_vz[zslot][li] = mzv * ir;
 #endif
                 }
             }
@@ -576,7 +590,7 @@ __global__ __launch_bounds__(TX *TY) void k_lagr(const T *__restrict__ Wst, T *_
             if (need_vel) {
                 __syncthreads();
                 // transverse velocity of the own column at plane m-2
-                const T *V = s_vz[slot];
+                const T *V = s_vz[zslot];
                 const int l = (ty + 1) * VW + tx + 1;
                 const T vt = tmpl9(V[l + 1 + VW], V[l + 1 - VW], V[l - 1 + VW], V[l - 1 - VW], V[l + 1], V[l - 1],
                                    V[l + VW], V[l - VW], V[l]);
@@ -602,10 +616,12 @@ __global__ __launch_bounds__(TX *TY) void k_lagr(const T *__restrict__ Wst, T *_
             __syncthreads();
         }
 
-        // ---- x / y directions of plane k ----
+        // ---- x / y directions of plane k, G fields per pass ----
         T acc[NF];
-        for (int f = 0; f < NF; f++) {
-            // cross tile of field f (and sqrt(rho) with the first field)
+#pragma unroll
+        for (int pass = 0; pass < NPASS; pass++) {
+            const int f0 = pass * G;
+            // cross tiles of the pass's fields
             for (int li = tid; li < PS; li += NT) {
                 const int ix = li % PW, iy = li / PW;
                 const int dx = ix - HX, dy = iy - HY;
@@ -615,41 +631,45 @@ __global__ __launch_bounds__(TX *TY) void k_lagr(const T *__restrict__ Wst, T *_
                 const int ax = map_index(x0 + dx, nx, gp.bc_lo[0], gp.bc_hi[0], fx);
                 const int ay = NDIM >= 2 ? map_index(y0 + dy, ny, gp.bc_lo[1], gp.bc_hi[1], fy) : 0;
                 const long long c = ((long long)k * ny + ay) * nx + ax;
-                T v = Wst[f * N + c];
-                if ((f == 1 && fx) || (NDIM >= 2 && f == 2 && fy)) v = -v;
-                s_f[li] = v;
-                if (f == 0) s_sq[li] = dsqrt(v);
+#pragma unroll
+                for (int g = 0; g < G; g++) {
+                    const int f = f0 + g;
+                    if (f >= NF) break;
+                    T v = Wst[f * N + c];
+                    if ((f == 1 && fx) || (NDIM >= 2 && f == 2 && fy)) v = -v;
+                    s_f[g][li] = v;
+                }
             }
             __syncthreads();
-            if (f == 0) {
+            if (pass == 0) {
                 // interface velocities of the x and y interfaces of the plane
                 const int sm = NDIM == 3 ? ((k - 1) % 3 + 3) % 3 : 0;
                 const int s0 = NDIM == 3 ? (k % 3 + 3) % 3 : 0;
                 const int sp = NDIM == 3 ? ((k + 1) % 3 + 3) % 3 : 0;
-                for (int j = tid; j < NXI; j += NT) {
-                    const int ix = j % (TX + 1), cy = j / (TX + 1);
-                    T vt[2];
+                for (int j = tid; j < NXI + NYI; j += NT) {
+                    if (j < NXI) {
+                        const int ix = j % (TX + 1), cy = j / (TX + 1);
+                        T vt[2];
 #pragma unroll
-                    for (int u = 0; u < 2; u++) {
-                        const int l = (cy + 1) * VW + ix + u;  // tile-rel x = ix-1+u
-                        if constexpr (NDIM == 3) {
-                            const T *A = s_vx[sm], *B = s_vx[s0], *C = s_vx[sp];
-                            // transverse axes y (first) and z (second)
-                            vt[u] = tmpl9(C[l + VW], A[l + VW], C[l - VW], A[l - VW], B[l + VW], B[l - VW], C[l], A[l],
-                                          B[l]);
-                        } else if constexpr (NDIM == 2) {
-                            const T *B = s_vx[0];
-                            vt[u] = tmpl3(B[l + VW], B[l - VW], B[l]);
-                        } else {
-                            vt[u] = s_vx[0][ix + u];
+                        for (int u = 0; u < 2; u++) {
+                            const int l = (cy + 1) * VW + ix + u;  // tile-rel x = ix-1+u
+                            if constexpr (NDIM == 3) {
+                                const T *A = s_vx[sm], *B = s_vx[s0], *C = s_vx[sp];
+                                // transverse axes y (first) and z (second)
+                                vt[u] = tmpl9(C[l + VW], A[l + VW], C[l - VW], A[l - VW], B[l + VW], B[l - VW], C[l],
+                                              A[l], B[l]);
+                            } else if constexpr (NDIM == 2) {
+                                const T *B = s_vx[0];
+                                vt[u] = tmpl3(B[l + VW], B[l - VW], B[l]);
+                            } else {
+                                vt[u] = s_vx[0][ix + u];
+                            }
                         }
-                    }
-                    const int la = (cy + HY) * PW + ix - 1 + HX;
-                    xvh[j] = interface_velocity(vt[0], s_sq[la], vt[1], s_sq[la + 1]);
-                }
-                if constexpr (NDIM >= 2) {
-                    for (int j = tid; j < NYI; j += NT) {
-                        const int cx = j % TX, iy = j / TX;
+                        const int la = (cy + HY) * PW + ix - 1 + HX;
+                        xvh[j] = interface_velocity(vt[0], dsqrt(s_f[0][la]), vt[1], dsqrt(s_f[0][la + 1]));
+                    } else if constexpr (NDIM >= 2) {
+                        const int jj = j - NXI;
+                        const int cx = jj % TX, iy = jj / TX;
                         T vt[2];
 #pragma unroll
                         for (int u = 0; u < 2; u++) {
@@ -665,52 +685,111 @@ __global__ __launch_bounds__(TX *TY) void k_lagr(const T *__restrict__ Wst, T *_
                             }
                         }
                         const int la = (iy - 1 + HY) * PW + cx + HX;
-                        yvh[j] = interface_velocity(vt[0], s_sq[la], vt[1], s_sq[la + PW]);
+                        yvh[jj] = interface_velocity(vt[0], dsqrt(s_f[0][la]), vt[1], dsqrt(s_f[0][la + PW]));
                     }
                 }
             }
-            for (int j = tid; j < NXP; j += NT) {
-                const int cx = j % (TX + 2), cy = j / (TX + 2);
-                const int li = (cy + HY) * PW + cx + 2;
-                xq[j] = parabola5(s_f[li - 2], s_f[li - 1], s_f[li], s_f[li + 1], s_f[li + 2]);
-            }
-            if constexpr (NDIM >= 2) {
-                for (int j = tid; j < NYP; j += NT) {
-                    const int cx = j % TX, cy = j / TX;
-                    const int li = (cy - 1 + HY) * PW + cx + HX;
-                    yq[j] = parabola5(s_f[li - 2 * PW], s_f[li - PW], s_f[li], s_f[li + PW], s_f[li + 2 * PW]);
+            // interface values (Appendix step 1) at every face of the tile
+            for (int j = tid; j < NXQ + NYQ; j += NT) {
+                if (j < NXQ) {
+                    const int fxi = j % (TX + 3), cy = j / (TX + 3);
+                    const int l = (cy + HY) * PW + fxi;  // q of tile-rel cells fxi-3 .. fxi
+#pragma unroll
+                    for (int g = 0; g < G; g++) {
+                        if (f0 + g >= NF) break;
+                        const T *q = s_f[g];
+                        const T da = limited_slope(q[l], q[l + 1], q[l + 2]);
+                        const T db = limited_slope(q[l + 1], q[l + 2], q[l + 3]);
+                        s_qx[g][j] = interface_value(q[l + 1], q[l + 2], da, db);
+                    }
+                } else if constexpr (NDIM >= 2) {
+                    const int jj = j - NXQ;
+                    const int cx = jj % TX, fyi = jj / TX;
+                    const int l = fyi * PW + cx + HX;  // rows fyi-3 .. fyi (tile-rel)
+#pragma unroll
+                    for (int g = 0; g < G; g++) {
+                        if (f0 + g >= NF) break;
+                        const T *q = s_f[g];
+                        const T da = limited_slope(q[l], q[l + PW], q[l + 2 * PW]);
+                        const T db = limited_slope(q[l + PW], q[l + 2 * PW], q[l + 3 * PW]);
+                        s_qy[g][jj] = interface_value(q[l + PW], q[l + 2 * PW], da, db);
+                    }
                 }
             }
             __syncthreads();
-            for (int j = tid; j < NXI; j += NT) {
-                const int ix = j % (TX + 1), cy = j / (TX + 1);
-                const int pa = cy * (TX + 2) + ix;
-                const T vh = xvh[j];
+            // upwind fluxes: only the upwind cell's parabola is needed.  They
+            // are kept in registers until every job has read the face values,
+            // then stored over the face arrays.
+            constexpr int NJF = (NXI + NYI + NT - 1) / NT;
+            T Fr[NJF][G];
+#pragma unroll
+            for (int r = 0; r < NJF; r++) {
+                const int j = tid + r * NT;
+                if (j < NXI) {
+                    const int ix = j % (TX + 1), cy = j / (TX + 1);
+                    const T vh = xvh[j];
+                    const bool left = vh >= T(0);
+                    const int u = left ? ix - 1 : ix;             // tile-rel upwind cell
+                    const int lq = (cy + HY) * PW + u + HX;       // its value
+                    const int lf = cy * (TX + 3) + u + 1;         // its left face
 #ifdef PPML_EXACT
-                const T z = dabs(vh) * tau / hx;
+                    const T z = dabs(vh) * tau / hx;
 #else
-                const T z = dabs(vh) * tohx;
+                    const T z = dabs(vh) * tohx;
 #endif
-                xF[j] = upwind_flux(vh, z, xq[pa], xq[pa + 1]);
-            }
-            if constexpr (NDIM >= 2) {
-                for (int j = tid; j < NYI; j += NT) {
-                    const int cx = j % TX, iy = j / TX;
-                    const int pa = iy * TX + cx;
-                    const T vh = yvh[j];
+#pragma unroll
+                    for (int g = 0; g < G; g++) {
+                        if (f0 + g >= NF) break;
+                        const Parab<T> p = monotonize(s_f[g][lq], s_qx[g][lf], s_qx[g][lf + 1]);
+                        const T fs = left ? avg_left(p.L, p.R, p.Q6, z) : avg_right(p.L, p.R, p.Q6, z);
+                        Fr[r][g] = vh * fs;
+                    }
+                } else if (NDIM >= 2 && j < NXI + NYI) {
+                    const int jj = j - NXI;
+                    const int cx = jj % TX, iy = jj / TX;
+                    const T vh = yvh[jj];
+                    const bool left = vh >= T(0);
+                    const int u = left ? iy - 1 : iy;
+                    const int lq = (u + HY) * PW + cx + HX;
+                    const int lf = (u + 1) * TX + cx;
 #ifdef PPML_EXACT
                     const T z = dabs(vh) * tau / hy;
 #else
                     const T z = dabs(vh) * tohy;
 #endif
-                    yF[j] = upwind_flux(vh, z, yq[pa], yq[pa + TX]);
+#pragma unroll
+                    for (int g = 0; g < G; g++) {
+                        if (f0 + g >= NF) break;
+                        const Parab<T> p = monotonize(s_f[g][lq], s_qy[g][lf], s_qy[g][lf + TX]);
+                        const T fs = left ? avg_left(p.L, p.R, p.Q6, z) : avg_right(p.L, p.R, p.Q6, z);
+                        Fr[r][g] = vh * fs;
+                    }
                 }
             }
             __syncthreads();
-            T a = PPML_DIV(xF[ty * (TX + 1) + tx + 1] - xF[ty * (TX + 1) + tx], hx, ihx);
-            if constexpr (NDIM >= 2) a = a + PPML_DIV(yF[(ty + 1) * TX + tx] - yF[ty * TX + tx], hy, ihy);
-            if constexpr (NDIM == 3) a = a + DFz[f];
-            acc[f] = a;
+#pragma unroll
+            for (int r = 0; r < NJF; r++) {
+                const int j = tid + r * NT;
+                if (j < NXI) {
+#pragma unroll
+                    for (int g = 0; g < G; g++)
+                        if (f0 + g < NF) s_Fx[g][j] = Fr[r][g];
+                } else if (NDIM >= 2 && j < NXI + NYI) {
+#pragma unroll
+                    for (int g = 0; g < G; g++)
+                        if (f0 + g < NF) s_Fy[g][j - NXI] = Fr[r][g];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int g = 0; g < G; g++) {
+                const int f = f0 + g;
+                if (f >= NF) break;
+                T a = PPML_DIV(s_Fx[g][ty * (TX + 1) + tx + 1] - s_Fx[g][ty * (TX + 1) + tx], hx, ihx);
+                if constexpr (NDIM >= 2) a = a + PPML_DIV(s_Fy[g][(ty + 1) * TX + tx] - s_Fy[g][ty * TX + tx], hy, ihy);
+                if constexpr (NDIM == 3) a = a + DFz[f];
+                acc[f] = a;
+            }
         }
 
         if (valid) {
