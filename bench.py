@@ -114,6 +114,74 @@ def run_precision(prob, prec, steps, warmup):
                 rho=rho, totals=tot)
 
 
+def run_batched(seed=0, steps=200):
+    """Batched configuration: 128 1-D Riemann problems (64-4096 cells) and
+    128 2-D periodic boxes (sides 32-256), FP32, 200 steps each.  Plain
+    per-grid launches against one batched launch sequence replayed from a HIP
+    graph; the two give the same bits for every grid."""
+    import numpy as np
+    import torch
+
+    from paper_1607_01105_amd import workloads as W
+    from paper_1607_01105_amd.ppml import Batch, Grid
+
+    probs = W.batch_mix(seed, steps=steps)
+    cells = sum(p.cells for p in probs)
+    stream = torch.cuda.Stream()
+    plain = [Grid.from_problem(p, prec="fp32", stream=stream) for p in probs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in plain:
+        g.step(steps)
+    for g in plain:
+        g.sync()
+    t_plain = time.perf_counter() - t0
+    b = Batch(len(probs))
+    slots = [b.admit(b.new_grid(p, prec="fp32")) for p in probs]
+    t0 = time.perf_counter()
+    b.step(steps, graph=True)  # records the graph, then replays it
+    b.sync()
+    t_first = time.perf_counter() - t0
+    for p, s in zip(probs, slots):
+        b.grids[s].set_primitive(p.rho, p.vx, p.vy, p.vz, p.p)
+    b.sync()
+    t0 = time.perf_counter()
+    b.step(steps, graph=True)
+    b.sync()
+    t_batch = time.perf_counter() - t0
+    same = all(np.array_equal(b.grids[s].get("rho"), g.get("rho")) for s, g in zip(slots, plain))
+    return {"workload": "128 1-D Riemann (64-4096 cells) + 128 2-D periodic (sides 32-256), FP32, 200 steps each",
+            "grids": len(probs), "cells": cells, "steps": steps,
+            "plain_zone_updates_per_s": cells * steps / t_plain, "plain_s": t_plain,
+            "batched_graph_zone_updates_per_s": cells * steps / t_batch, "batched_s": t_batch,
+            "batched_first_call_s": t_first, "speedup": t_plain / t_batch, "bitwise_equal_to_plain": bool(same)}
+
+
+def run_served(n_requests=60, load=0.5, seed=0, budget_gib=4.0, round_steps=50, capacity_zu_per_s=None):
+    """Served configuration: Poisson arrivals of 2-D (64^2-512^2) and 3-D
+    (64^3-192^3) periodic boxes with a high-pressure sphere, 50-500 steps,
+    FP32, admitted by an HBM budget; rate = load x the saturated capacity
+    (the headline throughput divided by the mean work per request)."""
+    import numpy as np
+
+    from paper_1607_01105_amd import workloads as W
+    from paper_1607_01105_amd.serve import Server
+
+    probe = W.served_trace(seed, 4000, 1.0)
+    mean_zu = float(np.mean([r.cells * r.steps for r in probe]))
+    cap_rps = capacity_zu_per_s / mean_zu
+    rate = load * cap_rps
+    trace = W.served_trace(seed, n_requests, rate)
+    srv = Server(budget_bytes=int(budget_gib * (1 << 30)), capacity=256, prec="fp32", round_steps=round_steps)
+    st = srv.run(trace)
+    return {"workload": "Poisson arrivals, 50% 2-D 64^2-512^2 / 50% 3-D 64^3-192^3 periodic boxes with one "
+                        "p=100 sphere, 50-500 steps, FP32", "requests": st["requests"], "rate_per_s": rate,
+            "load_vs_capacity": load, "budget_GiB": budget_gib, "round_steps": round_steps,
+            "latency_p50_s": st["latency_p50_s"], "latency_p99_s": st["latency_p99_s"],
+            "zone_updates_per_s": st["zone_updates_per_s"], "rounds": st["rounds"],
+            "data_wait_mean_s": st["data_wait_mean_s"]}
+
+
 def cpu_baseline(prob, max_seconds=30.0):
     """The FP64 oracle, untuned, on this host's cores: one step of the full
     256^3 workload (16.8M zone-updates)."""
@@ -139,6 +207,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched and served runs")
+    ap.add_argument("--serve-requests", type=int, default=60)
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one plain 256 MiB streaming kernel (torch.mul out-of-place: reads 256 MiB, "
                          "writes 256 MiB), the reference kernel for scaling the HBM byte counters")
@@ -221,6 +291,14 @@ def main():
         out["fp64"] = {"value": cells * args.steps / (r64["ms"] * 1e-3), "ms_per_step": r64["ms"] / args.steps,
                        "kernels_ms": {"euler": r64["ms_euler"], "lagr": r64["ms_lagr"]}}
         out["l1_rho_fp32_vs_fp64"] = float(np.sum(np.abs(res["fp32"]["rho"] - r64["rho"])) / np.sum(np.abs(r64["rho"])))
+    if not args.no_batch and "fp32" in res:
+        print("[bench] batched configuration", file=sys.stderr, flush=True)
+        out["batched"] = run_batched()
+        print(f"[bench] batched: {out['batched']['speedup']:.1f}x over plain launches", file=sys.stderr, flush=True)
+        print("[bench] served configuration", file=sys.stderr, flush=True)
+        out["served"] = run_served(n_requests=args.serve_requests, capacity_zu_per_s=value)
+        print(f"[bench] served: p50 {out['served']['latency_p50_s']:.3f} s, p99 {out['served']['latency_p99_s']:.3f} s",
+              file=sys.stderr, flush=True)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob)

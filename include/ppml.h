@@ -162,6 +162,52 @@ const char *ppml_last_error(void);
 int ppml_set_timing(ppml_grid *g, int32_t cap);
 int ppml_get_timing(ppml_grid *g, double *ms_euler, double *ms_lagr, int64_t *nsteps);
 
+/* ---- Batches: many independent grids stepped together ------------------
+ * A batch steps all its grids in the same kernel launches (one Eulerian and
+ * one Lagrangian launch per step and dimensionality present), optionally
+ * recorded once into a HIP graph and replayed.  Each grid keeps its own
+ * time step (Sec. 2.1 CFL condition of its own state), time, maxima and
+ * error word, so a grid's results are the same alone and in any batch.
+ * Grids keep their caller-owned memory; the batch owns two small tables
+ * (device and pinned host, capacity entries).  All grids of a batch share
+ * one precision.  Batch calls synchronize the batch stream before changing
+ * membership or staging step counts. */
+typedef struct ppml_batch ppml_batch;
+
+/* Create a batch of up to capacity grids that steps on hip_stream (must not
+ * be the legacy NULL stream when graphs are used).  budget_bytes > 0 caps the
+ * summed state + scratch bytes of the admitted grids.
+ * Errors: PPML_EINVAL, PPML_ENOMEM, PPML_EHIP. */
+int ppml_batch_create(int32_t capacity, size_t budget_bytes, void *hip_stream, ppml_batch **out);
+
+/* Admit a grid whose state is set; *slot receives its slot.  While admitted
+ * the grid is stepped only by the batch (ppml_step returns PPML_ESTATE); its
+ * get/set/totals calls still work.  Errors: PPML_EBUDGET (budget or capacity
+ * exhausted), PPML_ESTATE (already in a batch, state not set), PPML_EINVAL
+ * (other device or precision). */
+int ppml_batch_admit(ppml_batch *b, ppml_grid *g, int32_t *slot);
+
+/* Remove the grid in slot from the batch (after the batch's queued work). */
+int ppml_batch_retire(ppml_batch *b, int32_t slot);
+
+/* Enqueue nsteps steps for every admitted grid; steps_per_slot (indexed by
+ * slot, may be NULL) gives each grid's own count in [0, nsteps]: a grid stops
+ * after its count (its remaining launches are no-ops).  dt_fixed and t_stop
+ * as in ppml_step.  use_graph != 0 records the launches of nsteps steps into a
+ * HIP graph (re-recorded after membership or nsteps change) and replays it.
+ * Errors: PPML_EINVAL, PPML_EHIP. */
+int ppml_batch_step(ppml_batch *b, int32_t nsteps, const int32_t *steps_per_slot, double dt_fixed, double t_stop,
+                    int32_t use_graph);
+
+/* Synchronize; PPML_ENONFINITE if any admitted grid flagged a non-physical state. */
+int ppml_batch_sync(ppml_batch *b);
+
+/* Number of admitted grids and their summed state + scratch bytes. */
+int ppml_batch_info(ppml_batch *b, int32_t *count, size_t *bytes_in_use);
+
+/* Destroy the batch (admitted grids become free-standing again). */
+int ppml_batch_destroy(ppml_batch *b);
+
 /* Library version (major*10000 + minor*100 + patch). */
 int ppml_version(void);
 

@@ -124,7 +124,7 @@ struct ppml_grid {
     Ctrl *ctrl;
     double *partial;
     double *totals;
-    long long step_count;  // steps enqueued (selects the CFL slot)
+    bool in_batch;         // admitted to a batch: stepped only by the batch
     bool has_state;
     std::vector<hipEvent_t> ev;  // 3 events per timed step
     long long timed;             // steps recorded since the last read
@@ -132,18 +132,18 @@ struct ppml_grid {
 
 namespace {
 
-template <typename T> void launch_speeds(ppml_grid *g, int slot)
+template <typename T> void launch_speeds(ppml_grid *g)
 {
     const T *U = (const T *)g->state;
     int nb = (int)std::min<long long>(4096, (g->gp.ncell + 255) / 256);
     switch (g->d.ndim) {
-    case 1: k_speeds<T, 1><<<nb, 256, 0, g->stream>>>(U, g->gp, g->ctrl, slot); break;
-    case 2: k_speeds<T, 2><<<nb, 256, 0, g->stream>>>(U, g->gp, g->ctrl, slot); break;
-    default: k_speeds<T, 3><<<nb, 256, 0, g->stream>>>(U, g->gp, g->ctrl, slot); break;
+    case 1: k_speeds<T, 1><<<nb, 256, 0, g->stream>>>(U, g->gp, g->ctrl); break;
+    case 2: k_speeds<T, 2><<<nb, 256, 0, g->stream>>>(U, g->gp, g->ctrl); break;
+    default: k_speeds<T, 3><<<nb, 256, 0, g->stream>>>(U, g->gp, g->ctrl); break;
     }
 }
 
-template <typename T> void launch_step(ppml_grid *g, const StepArgs &sa, hipEvent_t *ev)
+template <typename T> void launch_step(ppml_grid *g, hipEvent_t *ev)
 {
     // ev (may be NULL): events recorded before, between and after the kernels
     const T *U = (const T *)g->state;
@@ -153,15 +153,15 @@ template <typename T> void launch_step(ppml_grid *g, const StepArgs &sa, hipEven
     const int nb = gp.tiles[0] * gp.tiles[1] * gp.tiles[2];
     if (ev) (void)hipEventRecord(ev[0], g->stream);
     switch (g->d.ndim) {
-    case 1: k_euler<T, 1, T1X, 1><<<nb, T1X, 0, g->stream>>>(U, W, gp, g->ctrl, sa); break;
-    case 2: k_euler<T, 2, T2X, T2Y><<<nb, T2X * T2Y, 0, g->stream>>>(U, W, gp, g->ctrl, sa); break;
-    default: k_euler<T, 3, T3X, T3Y><<<nb, T3X * T3Y, 0, g->stream>>>(U, W, gp, g->ctrl, sa); break;
+    case 1: k_euler<T, 1, T1X, 1><<<nb, T1X, 0, g->stream>>>(U, W, gp, g->ctrl); break;
+    case 2: k_euler<T, 2, T2X, T2Y><<<nb, T2X * T2Y, 0, g->stream>>>(U, W, gp, g->ctrl); break;
+    default: k_euler<T, 3, T3X, T3Y><<<nb, T3X * T3Y, 0, g->stream>>>(U, W, gp, g->ctrl); break;
     }
     if (ev) (void)hipEventRecord(ev[1], g->stream);
     switch (g->d.ndim) {
-    case 1: k_lagr<T, 1, T1X, 1, LG<T>::g><<<nb, T1X, 0, g->stream>>>(W, Us, gp, g->ctrl, sa); break;
-    case 2: k_lagr<T, 2, T2X, T2Y, LG<T>::g><<<nb, T2X * T2Y, 0, g->stream>>>(W, Us, gp, g->ctrl, sa); break;
-    default: k_lagr<T, 3, T3X, T3Y, LG<T>::g><<<nb, T3X * T3Y, 0, g->stream>>>(W, Us, gp, g->ctrl, sa); break;
+    case 1: k_lagr<T, 1, T1X, 1, LG<T>::g><<<nb, T1X, 0, g->stream>>>(W, Us, gp, g->ctrl); break;
+    case 2: k_lagr<T, 2, T2X, T2Y, LG<T>::g><<<nb, T2X * T2Y, 0, g->stream>>>(W, Us, gp, g->ctrl); break;
+    default: k_lagr<T, 3, T3X, T3Y, LG<T>::g><<<nb, T3X * T3Y, 0, g->stream>>>(W, Us, gp, g->ctrl); break;
     }
     if (ev) (void)hipEventRecord(ev[2], g->stream);
 }
@@ -199,16 +199,15 @@ int finish_set(ppml_grid *g, double t, double rho_mean0)
     HIPCHK(hipGetLastError());
     if (g->d.prec == PPML_FP64) {
         launch_totals<double>(g, rho_mean0 > 0.0 ? 0.0 : (double)g->gp.ncell);
-        launch_speeds<double>(g, 0);
+        launch_speeds<double>(g);
     } else {
         launch_totals<float>(g, rho_mean0 > 0.0 ? 0.0 : (double)g->gp.ncell);
-        launch_speeds<float>(g, 0);
+        launch_speeds<float>(g);
     }
     HIPCHK(hipGetLastError());
     if (rho_mean0 > 0.0)
         HIPCHK(hipMemcpyAsync(&g->ctrl->rho_mean0, &rho_mean0, sizeof(double), hipMemcpyHostToDevice, g->stream));
     HIPCHK(hipStreamSynchronize(g->stream));
-    g->step_count = 0;
     g->has_state = true;
     return PPML_OK;
 }
@@ -303,7 +302,7 @@ int ppml_create(const ppml_desc *d, void *state_dev, void *scratch_dev, void *hi
         gp.tiles[2] = (gp.n[2] + cz - 1) / cz;
     }
     g->has_state = false;
-    g->step_count = 0;
+    g->in_batch = false;
     g->timed = 0;
     *out = g;
     return PPML_OK;
@@ -403,17 +402,15 @@ int ppml_step(ppml_grid *g, int32_t nsteps, double dt_fixed, double t_stop)
     if (nsteps < 0) return fail(PPML_EINVAL, "nsteps must be >= 0");
     if (!g->has_state) return fail(PPML_ESTATE, "state was never set");
     if (!std::isfinite(dt_fixed) || !std::isfinite(t_stop)) return fail(PPML_EINVAL, "dt_fixed and t_stop must be finite");
+    if (nsteps == 0) return PPML_OK;
+    if (g->in_batch) return fail(PPML_ESTATE, "grid is stepped by its batch");
+    k_set_run<<<1, 1, 0, g->stream>>>(g->ctrl, dt_fixed, t_stop, (long long)nsteps);
     for (int s = 0; s < nsteps; s++) {
-        StepArgs sa;
-        sa.dt_fixed = dt_fixed;
-        sa.t_stop = t_stop;
-        sa.slot = (int)(g->step_count & 1);
         hipEvent_t *ev = nullptr;
         if ((size_t)(3 * (g->timed + 1)) <= g->ev.size()) ev = &g->ev[3 * g->timed];
-        if (g->d.prec == PPML_FP64) launch_step<double>(g, sa, ev);
-        else launch_step<float>(g, sa, ev);
+        if (g->d.prec == PPML_FP64) launch_step<double>(g, ev);
+        else launch_step<float>(g, ev);
         if (ev) g->timed++;
-        g->step_count++;
     }
     HIPCHK(hipGetLastError());
     return PPML_OK;
@@ -440,7 +437,7 @@ int ppml_max_speeds(ppml_grid *g, double *vmax, double *cmax)
     Ctrl c;
     HIPCHK(hipMemcpyAsync(&c, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, g->stream));
     HIPCHK(hipStreamSynchronize(g->stream));
-    int slot = (int)(g->step_count & 1);
+    int slot = c.slot_cur;
     double v, cs;
     unsigned long long vb = c.vmax_bits[slot], cb = c.cmax_bits[slot];
     memcpy(&v, &vb, sizeof v);
@@ -544,6 +541,7 @@ int ppml_get_timing(ppml_grid *g, double *ms_euler, double *ms_lagr, int64_t *ns
 int ppml_destroy(ppml_grid *g)
 {
     if (!g) return fail(PPML_EINVAL, "grid is NULL");
+    if (g->in_batch) return fail(PPML_ESTATE, "retire the grid from its batch first");
     (void)hipStreamSynchronize(g->stream);
     for (hipEvent_t e : g->ev) (void)hipEventDestroy(e);
     delete g;
@@ -567,5 +565,269 @@ const char *ppml_strerror(int status)
 const char *ppml_last_error(void) { return g_err; }
 
 int ppml_version(void) { return 100; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+struct ppml_batch {
+    hipStream_t stream;
+    int device;
+    int capacity;
+    size_t budget;   // 0: unlimited
+    size_t in_use;   // state + scratch bytes of the admitted grids
+    int prec;        // precision shared by all admitted grids (-1: none yet)
+    std::vector<ppml_grid *> slots;
+    BatchEntry *d_ents;   // device table, grouped by dimensionality
+    int *d_steps;         // device per-entry step counts
+    BatchEntry *h_ents;   // pinned host copies
+    int *h_steps;
+    std::vector<int> entry_slot;
+    int goff[4], gn[4], gtiles[4];
+    bool dirty;
+    long long version;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    int graph_nsteps;
+    long long graph_version;
+};
+
+namespace {
+
+size_t grid_bytes(const ppml_grid *g) { return ppml_state_bytes(&g->d) + ppml_scratch_bytes(&g->d); }
+
+int batch_rebuild(ppml_batch *b)
+{
+    int n = 0;
+    b->entry_slot.clear();
+    for (int nd = 1; nd <= 3; nd++) {
+        b->goff[nd] = n;
+        int tiles = 0;
+        for (int s = 0; s < b->capacity; s++) {
+            ppml_grid *g = b->slots[s];
+            if (!g || g->d.ndim != nd) continue;
+            BatchEntry &e = b->h_ents[n];
+            e.gp = g->gp;
+            e.state = g->state;
+            e.half = g->half;
+            e.ctrl = g->ctrl;
+            e.tile0 = tiles;
+            e.pad = 0;
+            tiles += g->gp.tiles[0] * g->gp.tiles[1] * g->gp.tiles[2];
+            b->entry_slot.push_back(s);
+            n++;
+        }
+        b->gn[nd] = n - b->goff[nd];
+        b->gtiles[nd] = tiles;
+    }
+    if (n > 0) {
+        HIPCHK(hipMemcpyAsync(b->d_ents, b->h_ents, (size_t)n * sizeof(BatchEntry), hipMemcpyHostToDevice, b->stream));
+        HIPCHK(hipStreamSynchronize(b->stream));
+    }
+    b->dirty = false;
+    b->version++;
+    return PPML_OK;
+}
+
+template <typename T> void batch_enqueue(ppml_batch *b, int nsteps)
+{
+    for (int s = 0; s < nsteps; s++) {
+        if (b->gn[1]) k_euler_batch<T, 1, T1X, 1><<<b->gtiles[1], T1X, 0, b->stream>>>(b->d_ents + b->goff[1], b->gn[1]);
+        if (b->gn[2])
+            k_euler_batch<T, 2, T2X, T2Y><<<b->gtiles[2], T2X * T2Y, 0, b->stream>>>(b->d_ents + b->goff[2], b->gn[2]);
+        if (b->gn[3])
+            k_euler_batch<T, 3, T3X, T3Y><<<b->gtiles[3], T3X * T3Y, 0, b->stream>>>(b->d_ents + b->goff[3], b->gn[3]);
+        if (b->gn[1])
+            k_lagr_batch<T, 1, T1X, 1, LG<T>::g><<<b->gtiles[1], T1X, 0, b->stream>>>(b->d_ents + b->goff[1], b->gn[1]);
+        if (b->gn[2])
+            k_lagr_batch<T, 2, T2X, T2Y, LG<T>::g>
+                <<<b->gtiles[2], T2X * T2Y, 0, b->stream>>>(b->d_ents + b->goff[2], b->gn[2]);
+        if (b->gn[3])
+            k_lagr_batch<T, 3, T3X, T3Y, LG<T>::g>
+                <<<b->gtiles[3], T3X * T3Y, 0, b->stream>>>(b->d_ents + b->goff[3], b->gn[3]);
+    }
+}
+
+void batch_drop_graph(ppml_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_nsteps = -1;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ppml_batch_create(int32_t capacity, size_t budget_bytes, void *hip_stream, ppml_batch **out)
+{
+    if (!out) return fail(PPML_EINVAL, "out is NULL");
+    if (capacity < 1 || capacity > 65536) return fail(PPML_EINVAL, "capacity must be in [1, 65536]");
+    ppml_batch *b = new (std::nothrow) ppml_batch();
+    if (!b) return fail(PPML_ENOMEM, "host allocation failed");
+    b->stream = (hipStream_t)hip_stream;
+    HIPCHK(hipGetDevice(&b->device));
+    b->capacity = capacity;
+    b->budget = budget_bytes;
+    b->in_use = 0;
+    b->prec = -1;
+    b->slots.assign(capacity, nullptr);
+    b->d_ents = nullptr;
+    b->d_steps = nullptr;
+    b->h_ents = nullptr;
+    b->h_steps = nullptr;
+    b->dirty = true;
+    b->version = 0;
+    b->graph = nullptr;
+    b->exec = nullptr;
+    b->graph_nsteps = -1;
+    b->graph_version = -1;
+    hipError_t e = hipMalloc(&b->d_ents, (size_t)capacity * sizeof(BatchEntry));
+    if (e == hipSuccess) e = hipMalloc(&b->d_steps, (size_t)capacity * sizeof(int));
+    if (e == hipSuccess) e = hipHostMalloc(&b->h_ents, (size_t)capacity * sizeof(BatchEntry), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(&b->h_steps, (size_t)capacity * sizeof(int), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        if (b->d_ents) (void)hipFree(b->d_ents);
+        if (b->d_steps) (void)hipFree(b->d_steps);
+        if (b->h_ents) (void)hipHostFree(b->h_ents);
+        if (b->h_steps) (void)hipHostFree(b->h_steps);
+        delete b;
+        return fail(PPML_ENOMEM, "batch tables: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    return PPML_OK;
+}
+
+int ppml_batch_admit(ppml_batch *b, ppml_grid *g, int32_t *slot)
+{
+    if (!b || !g) return fail(PPML_EINVAL, "batch and grid are required");
+    if (g->in_batch) return fail(PPML_ESTATE, "grid already belongs to a batch");
+    if (!g->has_state) return fail(PPML_ESTATE, "grid state was never set");
+    if (g->device != b->device) return fail(PPML_EINVAL, "grid and batch live on different devices");
+    if (b->prec >= 0 && g->d.prec != b->prec) return fail(PPML_EINVAL, "all grids of a batch share one precision");
+    const size_t need = grid_bytes(g);
+    if (b->budget > 0 && b->in_use + need > b->budget)
+        return fail(PPML_EBUDGET, "admitting %zu bytes would exceed the budget (%zu of %zu in use)", need, b->in_use,
+                    b->budget);
+    int s = -1;
+    for (int i = 0; i < b->capacity; i++)
+        if (!b->slots[i]) {
+            s = i;
+            break;
+        }
+    if (s < 0) return fail(PPML_EBUDGET, "batch is full (%d grids)", b->capacity);
+    HIPCHK(hipStreamSynchronize(b->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    b->slots[s] = g;
+    b->in_use += need;
+    b->prec = g->d.prec;
+    g->in_batch = true;
+    b->dirty = true;
+    if (slot) *slot = s;
+    return PPML_OK;
+}
+
+int ppml_batch_retire(ppml_batch *b, int32_t slot)
+{
+    if (!b) return fail(PPML_EINVAL, "batch is NULL");
+    if (slot < 0 || slot >= b->capacity || !b->slots[slot]) return fail(PPML_EINVAL, "slot %d is not in use", slot);
+    HIPCHK(hipStreamSynchronize(b->stream));
+    ppml_grid *g = b->slots[slot];
+    g->in_batch = false;
+    b->in_use -= grid_bytes(g);
+    b->slots[slot] = nullptr;
+    b->dirty = true;
+    bool any = false;
+    for (ppml_grid *x : b->slots) any = any || x;
+    if (!any) b->prec = -1;
+    return PPML_OK;
+}
+
+int ppml_batch_step(ppml_batch *b, int32_t nsteps, const int32_t *steps_per_slot, double dt_fixed, double t_stop,
+                    int32_t use_graph)
+{
+    if (!b) return fail(PPML_EINVAL, "batch is NULL");
+    if (nsteps < 0) return fail(PPML_EINVAL, "nsteps must be >= 0");
+    if (!std::isfinite(dt_fixed) || !std::isfinite(t_stop)) return fail(PPML_EINVAL, "dt_fixed and t_stop must be finite");
+    HIPCHK(hipStreamSynchronize(b->stream));  // staging buffers are free again
+    if (b->dirty) {
+        int rc = batch_rebuild(b);
+        if (rc) return rc;
+    }
+    const int n = (int)b->entry_slot.size();
+    if (n == 0 || nsteps == 0) return PPML_OK;
+    for (int i = 0; i < n; i++) {
+        int s = b->entry_slot[i];
+        int k = steps_per_slot ? steps_per_slot[s] : nsteps;
+        if (k < 0 || k > nsteps) return fail(PPML_EINVAL, "steps of slot %d must lie in [0, nsteps]", s);
+        b->h_steps[i] = k;
+    }
+    HIPCHK(hipMemcpyAsync(b->d_steps, b->h_steps, (size_t)n * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    k_batch_set_run<<<(n + 255) / 256, 256, 0, b->stream>>>(b->d_ents, n, b->d_steps, dt_fixed, t_stop);
+    HIPCHK(hipGetLastError());
+    const bool fp64 = b->prec == PPML_FP64;
+    if (use_graph) {
+        if (!b->exec || b->graph_version != b->version || b->graph_nsteps != nsteps) {
+            batch_drop_graph(b);
+            HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            if (fp64) batch_enqueue<double>(b, nsteps);
+            else batch_enqueue<float>(b, nsteps);
+            hipGraph_t gr = nullptr;
+            HIPCHK(hipStreamEndCapture(b->stream, &gr));
+            b->graph = gr;
+            HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+            b->graph_nsteps = nsteps;
+            b->graph_version = b->version;
+        }
+        HIPCHK(hipGraphLaunch(b->exec, b->stream));
+    } else {
+        if (fp64) batch_enqueue<double>(b, nsteps);
+        else batch_enqueue<float>(b, nsteps);
+        HIPCHK(hipGetLastError());
+    }
+    return PPML_OK;
+}
+
+int ppml_batch_sync(ppml_batch *b)
+{
+    if (!b) return fail(PPML_EINVAL, "batch is NULL");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    for (int s = 0; s < b->capacity; s++) {
+        ppml_grid *g = b->slots[s];
+        if (!g) continue;
+        int err = 0;
+        HIPCHK(hipMemcpy(&err, &g->ctrl->err, sizeof(int), hipMemcpyDeviceToHost));
+        if (err) return fail(PPML_ENONFINITE, "grid in slot %d produced a non-physical or non-finite value", s);
+    }
+    return PPML_OK;
+}
+
+int ppml_batch_info(ppml_batch *b, int32_t *count, size_t *bytes_in_use)
+{
+    if (!b) return fail(PPML_EINVAL, "batch is NULL");
+    int n = 0;
+    for (ppml_grid *x : b->slots) n += x ? 1 : 0;
+    if (count) *count = n;
+    if (bytes_in_use) *bytes_in_use = b->in_use;
+    return PPML_OK;
+}
+
+int ppml_batch_destroy(ppml_batch *b)
+{
+    if (!b) return fail(PPML_EINVAL, "batch is NULL");
+    (void)hipStreamSynchronize(b->stream);
+    batch_drop_graph(b);
+    for (ppml_grid *g : b->slots)
+        if (g) g->in_batch = false;
+    (void)hipFree(b->d_ents);
+    (void)hipFree(b->d_steps);
+    (void)hipHostFree(b->h_ents);
+    (void)hipHostFree(b->h_steps);
+    delete b;
+    return PPML_OK;
+}
 
 }  // extern "C"

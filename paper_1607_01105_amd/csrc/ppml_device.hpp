@@ -38,23 +38,27 @@ struct GridParams {
     int cz;        // planes per z chunk (3-D)
 };
 
-// Device control block of one grid (lives in the scratch area).
+// Device control block of one grid (lives in the scratch area).  Every
+// field is written by one thread of one kernel and read by the next kernel
+// on the stream, never by another work group of the kernel that writes it:
+// the Eulerian kernel reads slot_cur, t and the run parameters and writes
+// tau, slot_l and the other maxima slot; the Lagrangian kernel reads tau and
+// slot_l and writes t, the step counters and slot_cur.
 struct Ctrl {
     double t;             // simulation time
-    double tau;           // time step of the step in flight
+    double tau;           // time step of the step in flight (0: no-op step)
     double rho_mean0;     // FP64 initial mean density (vacuum reference)
     double dt_last;       // last time step taken
-    unsigned long long vmax_bits[2];  // max |v| of the state, as FP64 bits (two slots)
+    unsigned long long vmax_bits[2];  // max |v| of a state, as FP64 bits (two slots)
     unsigned long long cmax_bits[2];  // max c, as FP64 bits
     long long steps;      // steps taken
+    long long steps_left; // steps the current run may still take
+    double dt_fixed;      // run parameter: > 0 fixed time step
+    double t_stop;        // run parameter: > 0 end time
     int err;              // sticky error word (bit 0: non-physical state)
+    int slot_cur;         // slot holding the maxima of the current state
+    int slot_l;           // slot_cur of the step in flight (for the Lagrangian kernel)
     int pad;
-};
-
-struct StepArgs {
-    double dt_fixed;  // > 0: fixed time step
-    double t_stop;    // > 0: clip to end at t_stop
-    int slot;         // slot holding the maxima of the step's input state
 };
 
 #ifdef PPML_EXACT
@@ -263,18 +267,22 @@ __device__ __forceinline__ void potential_grad(const GridParams &gp, int i, int 
     for (int a = gp.ndim; a < 3; a++) g[a] = 0.0;
 }
 
-__device__ __forceinline__ double compute_tau(const Ctrl *c, const GridParams &gp, const StepArgs &sa)
+// Time step of the next step (Sec. 2.1 CFL condition, or the fixed step),
+// clipped to end at t_stop; 0 when the run has no steps left.
+__device__ __forceinline__ double compute_tau(const Ctrl *c, const GridParams &gp)
 {
+    if (c->steps_left <= 0) return 0.0;
     double tau;
-    if (sa.dt_fixed > 0.0) {
-        tau = sa.dt_fixed;
+    if (c->dt_fixed > 0.0) {
+        tau = c->dt_fixed;
     } else {
-        double vm = __longlong_as_double((long long)c->vmax_bits[sa.slot]);
-        double cm = __longlong_as_double((long long)c->cmax_bits[sa.slot]);
+        const int s = c->slot_cur;
+        double vm = __longlong_as_double((long long)c->vmax_bits[s]);
+        double cm = __longlong_as_double((long long)c->cmax_bits[s]);
         tau = gp.cfl_hmin / (vm + cm);
     }
-    if (sa.t_stop > 0.0) {
-        double rem = sa.t_stop - c->t;
+    if (c->t_stop > 0.0) {
+        double rem = c->t_stop - c->t;
         if (rem <= 0.0) tau = 0.0;
         else if (tau > rem) tau = rem;
     }
@@ -285,16 +293,21 @@ __device__ __forceinline__ double compute_tau(const Ctrl *c, const GridParams &g
 // 8 XCDs of the chip by their linear id; giving each XCD a contiguous range
 // of tiles (x fastest, then y, then z chunk) keeps the halo planes that
 // neighbouring tiles share in that XCD's L2.
+__device__ __forceinline__ void tile_decode(const GridParams &gp, int L, int &bx, int &by, int &bz)
+{
+    bx = L % gp.tiles[0];
+    const int t = L / gp.tiles[0];
+    by = t % gp.tiles[1];
+    bz = t / gp.tiles[1];
+}
+
 __device__ __forceinline__ void block_tile(const GridParams &gp, int &bx, int &by, int &bz)
 {
     const int nb = gp.tiles[0] * gp.tiles[1] * gp.tiles[2];
     const int b = blockIdx.x;
     const int x = b & 7, q = nb >> 3, r = nb & 7;
     const int L = x * q + (x < r ? x : r) + (b >> 3);
-    bx = L % gp.tiles[0];
-    const int t = L / gp.tiles[0];
-    by = t % gp.tiles[1];
-    bz = t / gp.tiles[1];
+    tile_decode(gp, L, bx, by, bz);
 }
 
 // Wave-wide maximum (wave64).

@@ -68,7 +68,20 @@ __global__ void k_ctrl_reset(Ctrl *ctrl, double t)
     ctrl->vmax_bits[0] = ctrl->vmax_bits[1] = 0ull;
     ctrl->cmax_bits[0] = ctrl->cmax_bits[1] = 0ull;
     ctrl->steps = 0;
+    ctrl->steps_left = 0;
+    ctrl->dt_fixed = 0.0;
+    ctrl->t_stop = 0.0;
     ctrl->err = 0;
+    ctrl->slot_cur = 0;
+    ctrl->slot_l = 0;
+}
+
+// Parameters of the next run of steps of one grid.
+__global__ void k_set_run(Ctrl *ctrl, double dt_fixed, double t_stop, long long nsteps)
+{
+    ctrl->dt_fixed = dt_fixed;
+    ctrl->t_stop = t_stop;
+    ctrl->steps_left = nsteps;
 }
 
 // Per-cell speeds |v| and c (Sec. 2.1) of a conserved state.
@@ -93,10 +106,11 @@ __device__ __forceinline__ void publish_max(Ctrl *ctrl, int slot, double v, doub
     }
 }
 
-// Maxima of |v| and c over the state into ctrl slot `slot` (first step).
+// Maxima of |v| and c over the state into the current slot (first step).
 template <typename T, int NDIM>
-__global__ void k_speeds(const T *__restrict__ U, GridParams gp, Ctrl *ctrl, int slot)
+__global__ void k_speeds(const T *__restrict__ U, GridParams gp, Ctrl *ctrl)
 {
+    const int slot = ctrl->slot_cur;
     const long long N = gp.ncell;
     const T gam = (T)gp.gamma, gm1 = (T)(gp.gamma - 1.0);
     double vm = 0.0, cm = 0.0;
@@ -168,8 +182,8 @@ __global__ __launch_bounds__(TOT_THREADS) void k_totals_final(const double *__re
 // Eulerian stage
 // ---------------------------------------------------------------------------
 template <typename T, int NDIM, int TX, int TY>
-__global__ __launch_bounds__(TX *TY) void k_euler(const T *__restrict__ U, T *__restrict__ Wst, GridParams gp,
-                                                   Ctrl *ctrl, StepArgs sa)
+__device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restrict__ Wst, const GridParams &gp,
+                                           Ctrl *ctrl, const int bx, const int by, const int bz, const bool lead)
 {
     constexpr int NT = TX * TY;
     constexpr int HX = GH;
@@ -192,28 +206,23 @@ __global__ __launch_bounds__(TX *TY) void k_euler(const T *__restrict__ U, T *__
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    int bx, by, bz;
-    block_tile(gp, bx, by, bz);
     const int x0 = bx * TX, y0 = by * TY;
     const int nx = gp.n[0], ny = gp.n[1], nz = gp.n[2];
     const long long N = gp.ncell;
 
-    const double tau_d = compute_tau(ctrl, gp, sa);
-    const bool lead = blockIdx.x == 0 && tid == 0;
-    if (!(tau_d > 0.0)) {
-        // step is a no-op: carry the maxima of the unchanged state forward
-        if (lead) {
-            ctrl->tau = 0.0;
-            ctrl->vmax_bits[sa.slot ^ 1] = ctrl->vmax_bits[sa.slot];
-            ctrl->cmax_bits[sa.slot ^ 1] = ctrl->cmax_bits[sa.slot];
-        }
-        return;
-    }
+    const double tau_d = compute_tau(ctrl, gp);
     if (lead) {
-        ctrl->tau = tau_d;
-        ctrl->vmax_bits[sa.slot ^ 1] = 0ull;
-        ctrl->cmax_bits[sa.slot ^ 1] = 0ull;
+        // publish the step for the Lagrangian kernel; a no-op step (tau = 0)
+        // leaves the state, its maxima slot and the time unchanged
+        const int s = ctrl->slot_cur;
+        ctrl->slot_l = s;
+        ctrl->tau = tau_d > 0.0 ? tau_d : 0.0;
+        if (tau_d > 0.0) {
+            ctrl->vmax_bits[s ^ 1] = 0ull;
+            ctrl->cmax_bits[s ^ 1] = 0ull;
+        }
     }
+    if (!(tau_d > 0.0)) return;
 
     const T gam = (T)gp.gamma;
     const T gm1 = (T)(gp.gamma - 1.0);
@@ -409,6 +418,15 @@ __global__ __launch_bounds__(TX *TY) void k_euler(const T *__restrict__ U, T *__
     }
 }
 
+template <typename T, int NDIM, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void k_euler(const T *__restrict__ U, T *__restrict__ Wst, GridParams gp,
+                                                   Ctrl *ctrl)
+{
+    int bx, by, bz;
+    block_tile(gp, bx, by, bz);
+    euler_body<T, NDIM, TX, TY>(U, Wst, gp, ctrl, bx, by, bz, blockIdx.x == 0 && threadIdx.x == 0);
+}
+
 // ---------------------------------------------------------------------------
 // Lagrangian stage + energy correction + CFL maxima
 // ---------------------------------------------------------------------------
@@ -427,8 +445,8 @@ template <typename T> __device__ __forceinline__ T tmpl3(T vp, T vm, T ctr)
 }
 
 template <typename T, int NDIM, int TX, int TY, int G>
-__global__ __launch_bounds__(TX *TY) void k_lagr(const T *__restrict__ Wst, T *__restrict__ U, GridParams gp,
-                                                  Ctrl *ctrl, StepArgs sa)
+__device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restrict__ U, const GridParams &gp,
+                                          Ctrl *ctrl, const int bx, const int by, const int bz, const bool lead)
 {
     constexpr int NT = TX * TY;
     constexpr int NF = 3 + NDIM;
@@ -468,14 +486,15 @@ __global__ __launch_bounds__(TX *TY) void k_lagr(const T *__restrict__ Wst, T *_
     const double tau_d = ctrl->tau;
     if (!(tau_d > 0.0)) return;
     const int tid = threadIdx.x;
-    if (blockIdx.x == 0 && tid == 0) {
+    const int sl = ctrl->slot_l;
+    if (lead) {
         ctrl->t = ctrl->t + tau_d;
         ctrl->dt_last = tau_d;
         ctrl->steps = ctrl->steps + 1;
+        ctrl->steps_left = ctrl->steps_left - 1;
+        ctrl->slot_cur = sl ^ 1;
     }
     const int tx = tid % TX, ty = tid / TX;
-    int bx, by, bz;
-    block_tile(gp, bx, by, bz);
     const int x0 = bx * TX, y0 = by * TY;
     const int nx = gp.n[0], ny = gp.n[1], nz = gp.n[2];
     const long long N = gp.ncell;
@@ -835,7 +854,76 @@ __global__ __launch_bounds__(TX *TY) void k_lagr(const T *__restrict__ Wst, T *_
             cmax = cmax > (double)cs ? cmax : (double)cs;
         }
     }
-    publish_max(ctrl, sa.slot ^ 1, vmax, cmax);
+    publish_max(ctrl, sl ^ 1, vmax, cmax);
+}
+
+template <typename T, int NDIM, int TX, int TY, int G>
+__global__ __launch_bounds__(TX *TY) void k_lagr(const T *__restrict__ Wst, T *__restrict__ U, GridParams gp,
+                                                  Ctrl *ctrl)
+{
+    int bx, by, bz;
+    block_tile(gp, bx, by, bz);
+    lagr_body<T, NDIM, TX, TY, G>(Wst, U, gp, ctrl, bx, by, bz, blockIdx.x == 0 && threadIdx.x == 0);
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches: many independent grids of one dimensionality step in the
+// same two kernel launches.  Each work group finds its grid in a table sorted
+// by first tile; every grid keeps its own control block (time step, time,
+// CFL maxima), so a grid's results do not depend on the other grids.
+// ---------------------------------------------------------------------------
+struct BatchEntry {
+    GridParams gp;
+    const void *state;
+    void *half;
+    Ctrl *ctrl;
+    int tile0;   // first work group of this grid in the launch
+    int pad;
+};
+
+__device__ __forceinline__ int batch_entry(const BatchEntry *__restrict__ ents, int ne, int b)
+{
+    int lo = 0, hi = ne - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ents[mid].tile0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T, int NDIM, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void k_euler_batch(const BatchEntry *__restrict__ ents, int ne)
+{
+    const BatchEntry *e = ents + batch_entry(ents, ne, blockIdx.x);
+    const int L = blockIdx.x - e->tile0;
+    int bx, by, bz;
+    tile_decode(e->gp, L, bx, by, bz);
+    euler_body<T, NDIM, TX, TY>((const T *)e->state, (T *)e->half, e->gp, e->ctrl, bx, by, bz,
+                                L == 0 && threadIdx.x == 0);
+}
+
+template <typename T, int NDIM, int TX, int TY, int G>
+__global__ __launch_bounds__(TX *TY) void k_lagr_batch(const BatchEntry *__restrict__ ents, int ne)
+{
+    const BatchEntry *e = ents + batch_entry(ents, ne, blockIdx.x);
+    const int L = blockIdx.x - e->tile0;
+    int bx, by, bz;
+    tile_decode(e->gp, L, bx, by, bz);
+    lagr_body<T, NDIM, TX, TY, G>((const T *)e->half, (T *)e->state, e->gp, e->ctrl, bx, by, bz,
+                                  L == 0 && threadIdx.x == 0);
+}
+
+// Run parameters of every grid of a batch (steps[i] < 0: same as nsteps).
+__global__ void k_batch_set_run(const BatchEntry *__restrict__ ents, int ne, const int *__restrict__ steps,
+                                double dt_fixed, double t_stop)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ne) return;
+    Ctrl *c = ents[i].ctrl;
+    c->dt_fixed = dt_fixed;
+    c->t_stop = t_stop;
+    c->steps_left = steps[i];
 }
 
 }  // namespace ppml

@@ -47,6 +47,8 @@ EXPORTS = (
     "ppml_state_bytes", "ppml_scratch_bytes", "ppml_create", "ppml_set_primitive", "ppml_set_conserved",
     "ppml_step", "ppml_get_time", "ppml_max_speeds", "ppml_get_conserved", "ppml_totals", "ppml_sync",
     "ppml_destroy", "ppml_strerror", "ppml_last_error", "ppml_version", "ppml_set_timing", "ppml_get_timing",
+    "ppml_batch_create", "ppml_batch_admit", "ppml_batch_retire", "ppml_batch_step", "ppml_batch_sync",
+    "ppml_batch_info", "ppml_batch_destroy",
 )
 
 _libs: dict[str, C.CDLL] = {}
@@ -81,6 +83,13 @@ def load(path: str | None = None) -> C.CDLL:
     lib.ppml_destroy.argtypes = [vp]
     lib.ppml_set_timing.argtypes = [vp, C.c_int32]
     lib.ppml_get_timing.argtypes = [vp, dp, dp, C.POINTER(C.c_int64)]
+    lib.ppml_batch_create.argtypes = [C.c_int32, C.c_size_t, vp, C.POINTER(vp)]
+    lib.ppml_batch_admit.argtypes = [vp, vp, C.POINTER(C.c_int32)]
+    lib.ppml_batch_retire.argtypes = [vp, C.c_int32]
+    lib.ppml_batch_step.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.c_double, C.c_double, C.c_int32]
+    lib.ppml_batch_sync.argtypes = [vp]
+    lib.ppml_batch_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_size_t)]
+    lib.ppml_batch_destroy.argtypes = [vp]
     lib.ppml_strerror.restype = C.c_char_p
     lib.ppml_strerror.argtypes = [C.c_int]
     lib.ppml_last_error.restype = C.c_char_p
@@ -258,3 +267,66 @@ class Grid:
             if t >= t_stop:
                 break
         return self.time()
+
+
+class Batch:
+    """Many grids stepped together by the batched kernels (include/ppml.h,
+    ppml_batch_*).  Grids must be created on the batch's stream (pass
+    ``stream=batch.stream``) and have their state set before admission."""
+
+    def __init__(self, capacity, budget_bytes=0, device="cuda", stream=None, exact=False):
+        import torch
+
+        self.lib = load(LIB_EXACT_PATH if exact else LIB_PATH)
+        self.exact = exact
+        self.device = torch.device(device)
+        # a dedicated stream: HIP graphs cannot be captured on the NULL stream
+        self.stream = stream or torch.cuda.Stream(self.device)
+        self.capacity = int(capacity)
+        h = C.c_void_p()
+        _check(self.lib, self.lib.ppml_batch_create(self.capacity, C.c_size_t(int(budget_bytes)),
+                                                    C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.grids = {}
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            self.lib.ppml_batch_destroy(h)
+            self.h = None
+
+    def new_grid(self, prob, prec="fp32", vacuum_ratio=1e-5):
+        """A grid for this batch (same stream and library), state set."""
+        return Grid.from_problem(prob, prec=prec, exact=self.exact, vacuum_ratio=vacuum_ratio, device=self.device,
+                                 stream=self.stream)
+
+    def admit(self, grid) -> int:
+        s = C.c_int32()
+        _check(self.lib, self.lib.ppml_batch_admit(self.h, grid.h, C.byref(s)))
+        self.grids[s.value] = grid
+        return s.value
+
+    def retire(self, slot):
+        _check(self.lib, self.lib.ppml_batch_retire(self.h, int(slot)))
+        return self.grids.pop(int(slot))
+
+    def step(self, nsteps, steps_per_slot=None, dt_fixed=0.0, t_stop=0.0, graph=True):
+        arr = None
+        if steps_per_slot is not None:
+            a = np.zeros(self.capacity, dtype=np.int32)
+            for s, k in (steps_per_slot.items() if isinstance(steps_per_slot, dict) else enumerate(steps_per_slot)):
+                a[int(s)] = int(k)
+            self._steps = a
+            arr = a.ctypes.data_as(C.POINTER(C.c_int32))
+        _check(self.lib, self.lib.ppml_batch_step(self.h, int(nsteps), arr, float(dt_fixed), float(t_stop),
+                                                  int(bool(graph))))
+
+    def sync(self):
+        _check(self.lib, self.lib.ppml_batch_sync(self.h))
+
+    def info(self):
+        n = C.c_int32()
+        b = C.c_size_t()
+        _check(self.lib, self.lib.ppml_batch_info(self.h, C.byref(n), C.byref(b)))
+        return n.value, b.value
+

@@ -1,0 +1,169 @@
+"""Serving loop: continuous batching of simulation requests on one GPU.
+
+Requests of a served trace arrive on a Poisson clock.  Each scheduler round
+
+1. admits arrived requests, oldest first, while the memory budget (state +
+   scratch of the admitted grids) and the batch capacity allow: the request's
+   initial state is copied to its device buffers and the grid joins the batch;
+2. advances every admitted grid by min(its remaining steps, round_steps) in
+   one batched launch sequence (every grid keeps its own CFL time step);
+3. retires grids whose steps are done: the final state is copied to the
+   host and the completion latency (arrival -> final state on the host) is
+   recorded; their memory is released for the next admissions.
+
+Requests that arrive while others are on the GPU join at the next round
+boundary, so new work overlaps the running work on the device.  The
+per-grid results do not depend on the mix (each grid's arithmetic and time
+step use only its own data), which the tests check bit for bit.
+
+The initial data of a request are produced by a small host thread pool ahead
+of the request's arrival (a client would send them with the request); time a
+request waits for its data after its arrival is counted in its latency and
+reported separately.
+"""
+from __future__ import annotations
+
+import collections
+import concurrent.futures as cf
+import dataclasses
+import time
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Completed:
+    rid: int
+    ndim: int
+    n: int
+    steps: int
+    arrival: float
+    admitted: float
+    done: float
+    data_wait: float
+    rho_checksum: float
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class Server:
+    """Continuous-batching server over the batch API of the HIP library."""
+
+    def __init__(self, budget_bytes: int = 4 << 30, capacity: int = 256, prec: str = "fp32", round_steps: int = 50,
+                 graph: bool = False, device: str = "cuda", prep_workers: int = 8, lookahead: int = 16,
+                 keep_results: bool = False, batch=None):
+        from .ppml import Batch
+
+        self.prec = prec
+        self.round_steps = int(round_steps)
+        self.graph = graph
+        self.budget = int(budget_bytes)
+        self.batch = batch if batch is not None else Batch(capacity, budget_bytes, device)
+        self.capacity = capacity
+        self.prep_workers = prep_workers
+        self.lookahead = lookahead
+        self.keep_results = keep_results
+        self.results: dict[int, np.ndarray] = {}
+
+    def _grid_bytes(self, req) -> int:
+        from .ppml import make_desc, ppml_scratch_bytes, ppml_state_bytes
+
+        d = make_desc(req.ndim, (req.n,) * req.ndim, (0.0,) * req.ndim, (1.0,) * req.ndim, 5.0 / 3.0, 0.3,
+                      prec=self.prec)
+        return ppml_state_bytes(d, self.batch.lib) + ppml_scratch_bytes(d, self.batch.lib)
+
+    def run(self, trace, time_scale: float = 1.0, log=None) -> dict:
+        """Serve the requests of `trace` (workloads.served_trace) in real time;
+        arrival times are multiplied by time_scale."""
+        reqs = sorted(trace, key=lambda r: r.arrival)
+        for r in reqs:
+            if self._grid_bytes(r) > self.budget:
+                raise ValueError(f"request {r.rid} needs more memory than the whole budget")
+        pool = cf.ThreadPoolExecutor(max_workers=self.prep_workers)
+        futures: dict[int, cf.Future] = {}
+        nxt = 0  # next request whose data are not yet submitted
+        pending = collections.deque(reqs)
+        waiting: collections.deque = collections.deque()
+        active: dict[int, list] = {}
+        done: list[Completed] = []
+        in_use = 0
+        zu_done = 0
+        rounds = 0
+        t0 = time.perf_counter()
+        clock = lambda: time.perf_counter() - t0  # noqa: E731
+
+        def prefetch():
+            nonlocal nxt
+            while nxt < len(reqs) and nxt < (len(done) + len(active) + self.lookahead):
+                r = reqs[nxt]
+                futures[r.rid] = pool.submit(r.problem)
+                nxt += 1
+
+        try:
+            while pending or waiting or active:
+                prefetch()
+                now = clock()
+                while pending and pending[0].arrival * time_scale <= now:
+                    waiting.append(pending.popleft())
+                # admission: FIFO while budget and capacity allow
+                while waiting and len(active) < self.capacity:
+                    r = waiting[0]
+                    need = self._grid_bytes(r)
+                    if in_use + need > self.budget:
+                        break
+                    t_req = clock()
+                    fut = futures.pop(r.rid, None)
+                    prob = fut.result() if fut is not None else r.problem()
+                    data_wait = max(0.0, clock() - max(t_req, r.arrival * time_scale))
+                    g = self.batch.new_grid(prob, prec=self.prec)
+                    slot = self.batch.admit(g)
+                    in_use += need
+                    active[slot] = [r, g, r.steps, clock(), data_wait, need]
+                    waiting.popleft()
+                    prefetch()
+                if not active:
+                    if pending:
+                        time.sleep(max(0.0, min(pending[0].arrival * time_scale - clock(), 0.05)))
+                    continue
+                steps = {s: min(a[2], self.round_steps) for s, a in active.items()}
+                self.batch.step(max(steps.values()), steps, graph=self.graph)
+                self.batch.sync()
+                rounds += 1
+                for s in list(active):
+                    a = active[s]
+                    a[2] -= steps[s]
+                    if a[2] > 0:
+                        continue
+                    r, g = a[0], a[1]
+                    self.batch.retire(s)
+                    rho = g.get("rho")
+                    t_done = clock()
+                    if self.keep_results:
+                        self.results[r.rid] = rho
+                    done.append(Completed(r.rid, r.ndim, r.n, r.steps, r.arrival * time_scale, a[3], t_done, a[4],
+                                          float(np.sum(rho))))
+                    zu_done += r.cells * r.steps
+                    in_use -= a[5]
+                    del active[s]
+                    if log:
+                        log(f"[serve] done rid={r.rid} {r.ndim}d n={r.n} steps={r.steps} "
+                            f"latency={t_done - r.arrival * time_scale:.3f}s active={len(active)}")
+        finally:
+            pool.shutdown(wait=True)
+        t_end = clock()
+        lat = np.array([c.latency for c in done])
+        first = min(c.arrival for c in done)
+        return {
+            "requests": len(done),
+            "rounds": rounds,
+            "wall_s": t_end - first,
+            "zone_updates": zu_done,
+            "zone_updates_per_s": zu_done / (t_end - first),
+            "latency_p50_s": float(np.percentile(lat, 50)),
+            "latency_p99_s": float(np.percentile(lat, 99)),
+            "latency_mean_s": float(lat.mean()),
+            "data_wait_mean_s": float(np.mean([c.data_wait for c in done])),
+            "completed": done,
+        }

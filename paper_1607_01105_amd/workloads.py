@@ -296,3 +296,77 @@ def blocks(ndim: int, n: int | tuple, seed: int, gamma=1.4, cfl=0.4, bc="periodi
     vs = [field(-0.5, 0.5) if a < ndim else np.zeros(shp) for a in range(3)]
     return Problem(f"blocks{ndim}d_s{seed}", ndim, n3, lo, hi, gamma, cfl, [(bc, bc)] * 3,
                    rho, vs[0], vs[1], vs[2], p, None, None, None)
+
+
+def batch_mix(seed: int = 0, n1d: int = 128, n2d: int = 128, steps: int = 200,
+              n1_range=(64, 4096), n2_range=(32, 256)) -> list:
+    """Independent grids of uneven sizes for one batched launch: n1d 1-D
+    Riemann problems (states drawn as in riemann_states, gamma 1.4, CFL 0.4,
+    outflow) with log-uniform sizes in n1_range, and n2d 2-D periodic boxes
+    with log-uniform sides in n2_range, density and pressure 1 + 0.1 * 8
+    random modes (separate draws), u = 0, gamma 5/3, CFL 0.3."""
+    rng = np.random.default_rng(seed)
+    probs = []
+    for i in range(n1d):
+        n = int(round(math.exp(rng.uniform(math.log(n1_range[0]), math.log(n1_range[1])))))
+        left = (rng.uniform(0.1, 1.0), rng.uniform(-1.0, 1.0), rng.uniform(0.1, 1.0))
+        right = (rng.uniform(0.1, 1.0), rng.uniform(-1.0, 1.0), rng.uniform(0.1, 1.0))
+        p = _two_state_1d(f"batch1d_{i}_n{n}", left, right, n, 0.0, 1.0, 0.5, 1.4, 0.4, "outflow", None)
+        p.nsteps = steps
+        probs.append(p)
+    for i in range(n2d):
+        nx = int(round(math.exp(rng.uniform(math.log(n2_range[0]), math.log(n2_range[1])))))
+        ny = int(round(math.exp(rng.uniform(math.log(n2_range[0]), math.log(n2_range[1])))))
+        n3, lo, hi = _grid(2, (nx, ny), (0.0, 0.0), (1.0, 1.0))
+        X, Y, Z = _mesh(n3, lo, hi)
+        rho = random_modes(rng, X, Y, Z, 2)
+        pr = random_modes(rng, X, Y, Z, 2)
+        z = np.zeros(X.shape)
+        probs.append(Problem(f"batch2d_{i}_{nx}x{ny}", 2, n3, lo, hi, 5.0 / 3.0, 0.3, [("periodic", "periodic")] * 3,
+                             np.ascontiguousarray(rho), z.copy(), z.copy(), z.copy(), np.ascontiguousarray(pr), None,
+                             steps, None))
+    return probs
+
+
+@dataclasses.dataclass
+class Request:
+    """One simulation request of a served trace (built lazily: a 192^3 state
+    is large)."""
+    rid: int
+    arrival: float      # seconds after the start of the trace
+    ndim: int
+    n: int
+    steps: int
+    seed: int
+    centre: tuple
+
+    @property
+    def cells(self) -> int:
+        return self.n ** self.ndim
+
+    def problem(self) -> Problem:
+        p = periodic_modes(self.n, seed=self.seed, ndim=self.ndim, sphere_p=100.0, sphere_r=0.1,
+                           sphere_centre=self.centre, nsteps=self.steps)
+        p.name = f"req{self.rid}_{self.ndim}d_{self.n}"
+        return p
+
+
+def served_trace(seed: int, n_requests: int, rate: float, n2_range=(64, 512), n3_range=(64, 192),
+                 steps_range=(50, 500)) -> list:
+    """Poisson arrivals at `rate` requests/s: half 2-D boxes with sides
+    log-uniform in n2_range, half 3-D cubes with sides log-uniform in n3_range,
+    each the periodic random-mode box with one p = 100 sphere (radius 0.1) at
+    a random centre, gamma 5/3, CFL 0.3, steps uniform in steps_range."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        ndim = 2 if rng.random() < 0.5 else 3
+        lo_, hi_ = n2_range if ndim == 2 else n3_range
+        n = int(round(math.exp(rng.uniform(math.log(lo_), math.log(hi_)))))
+        steps = int(rng.integers(steps_range[0], steps_range[1] + 1))
+        sd = int(rng.integers(0, 2 ** 31 - 1))
+        centre = tuple(float(c) for c in rng.uniform(0.0, 1.0, size=3))
+        out.append(Request(i, t, ndim, n, steps, sd, centre))
+    return out
