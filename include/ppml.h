@@ -67,6 +67,11 @@ typedef enum { PPML_RHO = 0, PPML_MX = 1, PPML_MY = 2, PPML_MZ = 3, PPML_ETOT = 
  *   PPML_POT_UNIFORM: Phi = gx x + gy y + gz z;  pot = {gx, gy, gz}      */
 typedef enum { PPML_POT_NONE = 0, PPML_POT_LOG = 1, PPML_POT_UNIFORM = 2 } ppml_potential;
 
+/* Descriptor flags.  PPML_FLAG_FIRST_ORDER: piecewise-constant states in both
+ * stages instead of parabolas -- the first-order scheme of Sec. 2.1 that the
+ * paper compares against (its shock-tube comparison). */
+enum { PPML_FLAG_FIRST_ORDER = 1 };
+
 typedef struct {
     int32_t ndim;          /* 1, 2 or 3                                             */
     int32_t prec;          /* ppml_precision of the stored state and the stencil    */
@@ -79,7 +84,7 @@ typedef struct {
     double vacuum_ratio;   /* Sec. 2.4 vacuum threshold relative to the initial
                               mean density (the paper: five orders, 1e-5)            */
     int32_t potential;     /* ppml_potential                                        */
-    int32_t reserved;      /* must be 0                                             */
+    int32_t flags;         /* PPML_FLAG_* bits; 0 = the paper's PPML scheme          */
     double pot[8];         /* potential parameters (see ppml_potential)             */
 } ppml_desc;
 

@@ -31,6 +31,10 @@ def build_one(out: str, exact: bool) -> str:
     flags = list(BASE_FLAGS)
     if exact:
         flags += ["-DPPML_EXACT=1", "-ffp-contract=off"]
+    else:
+        # FP32 division and square root at hardware rate (1 ulp); FP64 keeps
+        # correctly rounded division and square root
+        flags += ["-fno-hip-fp32-correctly-rounded-divide-sqrt"]
     tmp = out + ".tmp"
     cmd = [HIPCC, *flags, SRC, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -83,7 +83,7 @@ int validate(const ppml_desc *d)
     if (d->potential != PPML_POT_NONE && d->potential != PPML_POT_LOG && d->potential != PPML_POT_UNIFORM)
         return fail(PPML_EINVAL, "bad potential code");
     if (d->potential == PPML_POT_LOG && !(d->pot[2] > 0.0)) return fail(PPML_EINVAL, "log potential needs q > 0");
-    if (d->reserved != 0) return fail(PPML_EINVAL, "reserved must be 0");
+    if (d->flags & ~PPML_FLAG_FIRST_ORDER) return fail(PPML_EINVAL, "unknown flags 0x%x", d->flags);
     return PPML_OK;
 }
 
@@ -280,6 +280,7 @@ int ppml_create(const ppml_desc *d, void *state_dev, void *scratch_dev, void *hi
     gp.cfl_hmin = d->cfl * hmin;
     gp.vacuum_ratio = d->vacuum_ratio;
     gp.potential = d->potential;
+    gp.first_order = (d->flags & PPML_FLAG_FIRST_ORDER) ? 1 : 0;
     for (int i = 0; i < 8; i++) gp.pot[i] = d->pot[i];
     // tiles of the stage kernels; 3-D: z chunk small enough that the launch
     // has enough work groups to fill 256 CUs several times over

@@ -34,6 +34,7 @@ struct GridParams {
     int bc_lo[3], bc_hi[3];
     int potential;
     double pot[8];
+    int first_order;  // 1: piecewise-constant states (first-order scheme of Sec. 2.1)
     int tiles[3];  // work-group tiles along x, y and z chunks of the stage kernels
     int cz;        // planes per z chunk (3-D)
 };
@@ -168,6 +169,19 @@ template <typename T> __device__ __forceinline__ Parab<T> parabola5(T qm2, T qm1
     T l = interface_value(qm1, q0, dmm, dm0);
     T r = interface_value(q0, qp1, dm0, dmp);
     return monotonize(q0, l, r);
+}
+
+// State profile of a cell: the monotonised parabola, or the constant cell
+// value in the first-order scheme.
+template <typename T> __device__ __forceinline__ Parab<T> profile(int first_order, T c, T l, T r)
+{
+    if (first_order) return Parab<T>{c, c, T(0)};
+    return monotonize(c, l, r);
+}
+template <typename T> __device__ __forceinline__ Parab<T> profile5(int first_order, T qm2, T qm1, T q0, T qp1, T qp2)
+{
+    if (first_order) return Parab<T>{q0, q0, T(0)};
+    return parabola5(qm2, qm1, q0, qp1, qp2);
 }
 
 // Appendix: mean of a cell's parabola over the strip of z*h next to its

@@ -284,8 +284,8 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
             const T dp_new = limited_slope(qp0, qp1, qp2);
             const T qIv_new = interface_value(qv0, qv1, dmv, dv_new);
             const T qIp_new = interface_value(qp0, qp1, dmp, dp_new);
-            const Parab<T> pv_new = monotonize(qv0, qIv, qIv_new);
-            const Parab<T> pp_new = monotonize(qp0, qIp, qIp_new);
+            const Parab<T> pv_new = profile(gp.first_order, qv0, qIv, qIv_new);
+            const Parab<T> pp_new = profile(gp.first_order, qp0, qIp, qIp_new);
             dmv = dv_new; dmp = dp_new; qIv = qIv_new; qIp = qIp_new;
             // interface between planes m-3 and m-2
             const VP<T> vpz = riemann(sr0, sr1, rr0, rr1, pr0, pr1, pv_prev, pv_new, pp_prev, pp_new, gam, tau, hz,
@@ -340,15 +340,15 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
         for (int j = tid; j < NXP; j += NT) {
             const int cx = j % (TX + 2), cy = j / (TX + 2);
             const int li = (cy + HY) * PW + cx + 2;
-            xv[j] = parabola5(s_vx[li - 2], s_vx[li - 1], s_vx[li], s_vx[li + 1], s_vx[li + 2]);
-            xp[j] = parabola5(s_p[li - 2], s_p[li - 1], s_p[li], s_p[li + 1], s_p[li + 2]);
+            xv[j] = profile5(gp.first_order, s_vx[li - 2], s_vx[li - 1], s_vx[li], s_vx[li + 1], s_vx[li + 2]);
+            xp[j] = profile5(gp.first_order, s_p[li - 2], s_p[li - 1], s_p[li], s_p[li + 1], s_p[li + 2]);
         }
         if constexpr (NDIM >= 2) {
             for (int j = tid; j < NYP; j += NT) {
                 const int cx = j % TX, cy = j / TX;
                 const int li = (cy - 1 + HY) * PW + cx + HX;
-                yv[j] = parabola5(s_vy[li - 2 * PW], s_vy[li - PW], s_vy[li], s_vy[li + PW], s_vy[li + 2 * PW]);
-                yp[j] = parabola5(s_p[li - 2 * PW], s_p[li - PW], s_p[li], s_p[li + PW], s_p[li + 2 * PW]);
+                yv[j] = profile5(gp.first_order, s_vy[li - 2 * PW], s_vy[li - PW], s_vy[li], s_vy[li + PW], s_vy[li + 2 * PW]);
+                yp[j] = profile5(gp.first_order, s_p[li - 2 * PW], s_p[li - PW], s_p[li], s_p[li + PW], s_p[li + 2 * PW]);
             }
         }
         __syncthreads();
@@ -601,7 +601,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                 q2[f] = v;
                 const T dnew = limited_slope(q0[f], q1[f], q2[f]);
                 const T qInew = interface_value(q0[f], q1[f], dmq[f], dnew);
-                pnew[f] = monotonize(q0[f], qI[f], qInew);
+                pnew[f] = profile(gp.first_order, q0[f], qI[f], qInew);
                 dmq[f] = dnew;
                 qI[f] = qInew;
             }
@@ -637,6 +637,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
 
         // ---- x / y directions of plane k, G fields per pass ----
         T acc[NF];
+        T own[NF];  // U^{n+1/2} of the thread's own cell, read from the tiles
 #pragma unroll
         for (int pass = 0; pass < NPASS; pass++) {
             const int f0 = pass * G;
@@ -759,7 +760,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
 #pragma unroll
                     for (int g = 0; g < G; g++) {
                         if (f0 + g >= NF) break;
-                        const Parab<T> p = monotonize(s_f[g][lq], s_qx[g][lf], s_qx[g][lf + 1]);
+                        const Parab<T> p = profile(gp.first_order, s_f[g][lq], s_qx[g][lf], s_qx[g][lf + 1]);
                         const T fs = left ? avg_left(p.L, p.R, p.Q6, z) : avg_right(p.L, p.R, p.Q6, z);
                         Fr[r][g] = vh * fs;
                     }
@@ -779,7 +780,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
 #pragma unroll
                     for (int g = 0; g < G; g++) {
                         if (f0 + g >= NF) break;
-                        const Parab<T> p = monotonize(s_f[g][lq], s_qy[g][lf], s_qy[g][lf + TX]);
+                        const Parab<T> p = profile(gp.first_order, s_f[g][lq], s_qy[g][lf], s_qy[g][lf + TX]);
                         const T fs = left ? avg_left(p.L, p.R, p.Q6, z) : avg_right(p.L, p.R, p.Q6, z);
                         Fr[r][g] = vh * fs;
                     }
@@ -804,6 +805,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
             for (int g = 0; g < G; g++) {
                 const int f = f0 + g;
                 if (f >= NF) break;
+                own[f] = s_f[g][(ty + HY) * PW + tx + HX];
                 T a = PPML_DIV(s_Fx[g][ty * (TX + 1) + tx + 1] - s_Fx[g][ty * (TX + 1) + tx], hx, ihx);
                 if constexpr (NDIM >= 2) a = a + PPML_DIV(s_Fy[g][(ty + 1) * TX + tx] - s_Fy[g][ty * TX + tx], hy, ihy);
                 if constexpr (NDIM == 3) a = a + DFz[f];
@@ -815,7 +817,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
             const long long c = ((long long)k * ny + gy) * nx + gx;
             T fn[NF];
 #pragma unroll
-            for (int f = 0; f < NF; f++) fn[f] = Wst[f * N + c] - tau * acc[f];
+            for (int f = 0; f < NF; f++) fn[f] = own[f] - tau * acc[f];
             // total-energy correction (Sec. 2.4), FP64 arithmetic
             const double r = (double)fn[0];
             double mx = (double)fn[1];

@@ -21,6 +21,7 @@ PPML_FP32, PPML_FP64 = 0, 1
 PPML_PERIODIC, PPML_OUTFLOW, PPML_REFLECT = 0, 1, 2
 PPML_RHO, PPML_MX, PPML_MY, PPML_MZ, PPML_ETOT, PPML_EINT = 0, 1, 2, 3, 4, 5
 PPML_POT_NONE, PPML_POT_LOG, PPML_POT_UNIFORM = 0, 1, 2
+PPML_FLAG_FIRST_ORDER = 1
 
 BC = {"periodic": PPML_PERIODIC, "outflow": PPML_OUTFLOW, "reflect": PPML_REFLECT}
 PREC = {"fp32": PPML_FP32, "f32": PPML_FP32, "fp64": PPML_FP64, "f64": PPML_FP64}
@@ -32,7 +33,7 @@ class ppml_desc(C.Structure):
         ("ndim", C.c_int32), ("prec", C.c_int32), ("n", C.c_int64 * 3),
         ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("gamma", C.c_double), ("cfl", C.c_double),
         ("bc_lo", C.c_int32 * 3), ("bc_hi", C.c_int32 * 3), ("vacuum_ratio", C.c_double),
-        ("potential", C.c_int32), ("reserved", C.c_int32), ("pot", C.c_double * 8),
+        ("potential", C.c_int32), ("flags", C.c_int32), ("pot", C.c_double * 8),
     ]
 
 
@@ -108,7 +109,8 @@ def _check(lib, rc):
     return rc
 
 
-def make_desc(ndim, n, lo, hi, gamma, cfl, bc="periodic", prec="fp64", vacuum_ratio=1e-5, potential=None):
+def make_desc(ndim, n, lo, hi, gamma, cfl, bc="periodic", prec="fp64", vacuum_ratio=1e-5, potential=None,
+              first_order=False):
     d = ppml_desc()
     d.ndim = int(ndim)
     d.prec = PREC[prec] if isinstance(prec, str) else int(prec)
@@ -130,7 +132,7 @@ def make_desc(ndim, n, lo, hi, gamma, cfl, bc="periodic", prec="fp64", vacuum_ra
     d.cfl = float(cfl)
     d.vacuum_ratio = float(vacuum_ratio)
     d.potential = POT[potential[0]] if potential else PPML_POT_NONE
-    d.reserved = 0
+    d.flags = PPML_FLAG_FIRST_ORDER if first_order else 0
     if potential:
         for i, v in enumerate(potential[1:]):
             d.pot[i] = float(v)
@@ -171,11 +173,11 @@ class Grid:
     """One grid on the current GPU; state and scratch are torch tensors."""
 
     def __init__(self, ndim, n, lo, hi, gamma, cfl, bc="periodic", prec="fp64", vacuum_ratio=1e-5,
-                 potential=None, device="cuda", stream=None, exact=False):
+                 potential=None, device="cuda", stream=None, exact=False, first_order=False, lib_path=None):
         import torch
 
-        self.lib = load(LIB_EXACT_PATH if exact else LIB_PATH)
-        self.desc = make_desc(ndim, n, lo, hi, gamma, cfl, bc, prec, vacuum_ratio, potential)
+        self.lib = load(lib_path or (LIB_EXACT_PATH if exact else LIB_PATH))
+        self.desc = make_desc(ndim, n, lo, hi, gamma, cfl, bc, prec, vacuum_ratio, potential, first_order)
         self.ndim = int(ndim)
         self.ncell = int(self.desc.n[0] * self.desc.n[1] * self.desc.n[2])
         sb = ppml_state_bytes(self.desc, self.lib)
