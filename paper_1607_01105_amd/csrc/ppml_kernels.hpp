@@ -186,6 +186,7 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
                                            Ctrl *ctrl, const int bx, const int by, const int bz, const bool lead)
 {
     constexpr int NT = TX * TY;
+    constexpr int NF = 3 + NDIM;
     constexpr int HX = GH;
     constexpr int HY = NDIM >= 2 ? GH : 0;
     constexpr int PW = TX + 2 * HX;
@@ -249,6 +250,40 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
         z1 = z0 + gp.cz < nz ? z0 + gp.cz : nz;
     }
 
+    // per-field base pointers (uniform) and 32-bit cell offsets
+    const T *Uf[NF];
+    T *Wf[NF];
+#pragma unroll
+    for (int f = 0; f < NF; f++) {
+        Uf[f] = U + (size_t)f * (size_t)N;
+        Wf[f] = Wst + (size_t)f * (size_t)N;
+    }
+    const int plane = nx * ny;
+
+    // Cross-tile cells this thread stages on every plane: (y, x) offset of
+    // the boundary-mapped source cell (-1 where nothing is loaded) and the
+    // momentum flips, two bits per cell.  Only the plane index changes along
+    // z, so the maps are evaluated once.
+    constexpr int RC = (PS + NT - 1) / NT;
+    static_assert(2 * RC <= 32, "flip bits");
+    int ccode[RC];
+    unsigned flips = 0;
+#pragma unroll
+    for (int r = 0; r < RC; r++) {
+        const int li = tid + r * NT;
+        ccode[r] = -1;
+        if (li < PS) {
+            const int dx = li % PW - HX, dy = li / PW - HY;
+            if ((dy >= 0 && dy < TY) || (dx >= 0 && dx < TX)) {
+                int fx, fy = 0;
+                const int ax = map_index(x0 + dx, nx, gp.bc_lo[0], gp.bc_hi[0], fx);
+                const int ay = NDIM >= 2 ? map_index(y0 + dy, ny, gp.bc_lo[1], gp.bc_hi[1], fy) : 0;
+                ccode[r] = ay * nx + ax;
+                flips |= (unsigned)(fx | (fy << 1)) << (2 * r);
+            }
+        }
+    }
+
     // z pipeline registers (3-D): values of the thread's own column
     T qv0 = 1, qv1 = 1, qv2 = 1, qp0 = 1, qp1 = 1, qp2 = 1;  // q_{m-2}, q_{m-1}, q_m
     T dmv = 0, dmp = 0;                                      // slope at m-2
@@ -267,11 +302,11 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
         if constexpr (NDIM == 3) {
             int fz;
             const int mz = map_index(m, nz, gp.bc_lo[2], gp.bc_hi[2], fz);
-            const long long c = ((long long)mz * ny + cy_) * nx + cx_;
-            const T rho = U[c];
-            T mzv = U[3 * N + c];
+            const int c = mz * plane + cy_ * nx + cx_;
+            const T rho = Uf[0][c];
+            T mzv = Uf[3][c];
             if (fz) mzv = -mzv;
-            const T e = U[5 * N + c];
+            const T e = Uf[5][c];
             const T vz = mzv / rho;
             const T p = gm1 * e;
             const T s = dsqrt(rho);
@@ -301,19 +336,16 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
         }
 
         // ---- x / y directions of plane k from LDS ----
-        for (int li = tid; li < PS; li += NT) {
-            const int ix = li % PW, iy = li / PW;
-            const int dx = ix - HX, dy = iy - HY;
-            const bool cross = (dy >= 0 && dy < TY) || (dx >= 0 && dx < TX);
-            if (!cross) continue;
-            int fx, fy = 0;
-            const int ax = map_index(x0 + dx, nx, gp.bc_lo[0], gp.bc_hi[0], fx);
-            const int ay = NDIM >= 2 ? map_index(y0 + dy, ny, gp.bc_lo[1], gp.bc_hi[1], fy) : 0;
-            const long long c = ((long long)k * ny + ay) * nx + ax;
-            const T rho = U[c];
-            T mxv = U[N + c];
-            if (fx) mxv = -mxv;
-            const T e = U[(2 + NDIM) * N + c];
+#pragma unroll
+        for (int r = 0; r < RC; r++) {
+            if (ccode[r] < 0) continue;
+            const int li = tid + r * NT;
+            const unsigned fl = flips >> (2 * r);
+            const int c = k * plane + ccode[r];
+            const T rho = Uf[0][c];
+            T mxv = Uf[1][c];
+            if (fl & 1) mxv = -mxv;
+            const T e = Uf[2 + NDIM][c];
 #ifdef PPML_EXACT
             s_vx[li] = mxv / rho;
 #else
@@ -321,8 +353,8 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
             s_vx[li] = mxv * ir;
 #endif
             if constexpr (NDIM >= 2) {
-                T myv = U[2 * N + c];
-                if (fy) myv = -myv;
+                T myv = Uf[2][c];
+                if (fl & 2) myv = -myv;
 #ifdef PPML_EXACT
                 s_vy[li] = myv / rho;
 #else
@@ -386,14 +418,14 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
                 sPV = sPV + DPVz;
                 sV = sV + DVz;
             }
-            const long long c = ((long long)k * ny + gy) * nx + gx;
-            const T rho = U[c];
+            const int c = k * plane + gy * nx + gx;
+            const T rho = Uf[0][c];
             T mom[3];
-            mom[0] = U[N + c];
-            mom[1] = NDIM >= 2 ? U[2 * N + c] : T(0);
-            mom[2] = NDIM >= 3 ? U[3 * N + c] : T(0);
-            const T Et = U[(1 + NDIM) * N + c];
-            const T e = U[(2 + NDIM) * N + c];
+            mom[0] = Uf[1][c];
+            mom[1] = NDIM >= 2 ? Uf[2][c] : T(0);
+            mom[2] = NDIM >= 3 ? Uf[3][c] : T(0);
+            const T Et = Uf[1 + NDIM][c];
+            const T e = Uf[2 + NDIM][c];
             T mn[3];
             mn[0] = mom[0] - tau * DPx;
             mn[1] = mom[1] - tau * DPy;
@@ -408,12 +440,12 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
                 for (int ax = 0; ax < NDIM; ax++) mn[ax] = (T)((double)mn[ax] - tr * g[ax]);
                 Etn = (T)((double)Etn - tau_d * work);
             }
-            Wst[c] = rho;
-            Wst[N + c] = mn[0];
-            if constexpr (NDIM >= 2) Wst[2 * N + c] = mn[1];
-            if constexpr (NDIM >= 3) Wst[3 * N + c] = mn[2];
-            Wst[(1 + NDIM) * N + c] = Etn;
-            Wst[(2 + NDIM) * N + c] = en;
+            Wf[0][c] = rho;
+            Wf[1][c] = mn[0];
+            if constexpr (NDIM >= 2) Wf[2][c] = mn[1];
+            if constexpr (NDIM >= 3) Wf[3][c] = mn[2];
+            Wf[1 + NDIM][c] = Etn;
+            Wf[2 + NDIM][c] = en;
         }
     }
 }
@@ -475,8 +507,6 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
     static_assert(NXI <= NXQ && NYI <= NYQ + 1, "flux arrays must fit in the face arrays");
     T (*s_Fx)[NXQ] = s_qx;
     T (*s_Fy)[NYQ > 0 ? NYQ : 1] = s_qy;
-    __shared__ T xvh[NXI];
-    __shared__ T yvh[NYI > 0 ? NYI : 1];
     __shared__ T s_vx[NR][VS];
     __shared__ T s_vy[NDIM >= 2 ? NR : 1][NDIM >= 2 ? VS : 1];
     // v_z is only needed on the newest plane; two slots alternate so that a
@@ -519,6 +549,50 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
         z1 = z0 + gp.cz < nz ? z0 + gp.cz : nz;
     }
 
+    // per-field base pointers (uniform) and 32-bit cell offsets
+    const T *Wf[NF];
+#pragma unroll
+    for (int f = 0; f < NF; f++) Wf[f] = Wst + (size_t)f * (size_t)N;
+    const int plane = nx * ny;
+    const int own_off = cy_ * nx + cx_;
+
+    // Tile cells this thread stages on every plane: the (y, x) offset of the
+    // boundary-mapped source cell (-1 where nothing is loaded) and the
+    // momentum flips, two bits per cell (x, y).  Only the plane index changes
+    // along z, so the maps are evaluated once.
+    constexpr int RC = (PS + NT - 1) / NT;
+    constexpr int RV = (VS + NT - 1) / NT;
+    static_assert(2 * (RC + RV) <= 32, "flip bits");
+    int ccode[RC], vcode[RV];
+    unsigned flips = 0;
+#pragma unroll
+    for (int r = 0; r < RC; r++) {
+        const int li = tid + r * NT;
+        ccode[r] = -1;
+        if (li < PS) {
+            const int dx = li % PW - HX, dy = li / PW - HY;
+            if ((dy >= 0 && dy < TY) || (dx >= 0 && dx < TX)) {
+                int fx, fy = 0;
+                const int ax = map_index(x0 + dx, nx, gp.bc_lo[0], gp.bc_hi[0], fx);
+                const int ay = NDIM >= 2 ? map_index(y0 + dy, ny, gp.bc_lo[1], gp.bc_hi[1], fy) : 0;
+                ccode[r] = ay * nx + ax;
+                flips |= (unsigned)(fx | (fy << 1)) << (2 * r);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RV; r++) {
+        const int li = tid + r * NT;
+        vcode[r] = -1;
+        if (li < VS) {
+            int fx, fy = 0;
+            const int ax = map_index(x0 + li % VW - 1, nx, gp.bc_lo[0], gp.bc_hi[0], fx);
+            const int ay = NDIM >= 2 ? map_index(y0 + li / VW - 1, ny, gp.bc_lo[1], gp.bc_hi[1], fy) : 0;
+            vcode[r] = ay * nx + ax;
+            flips |= (unsigned)(fx | (fy << 1)) << (2 * (RC + r));
+        }
+    }
+
     // z pipeline registers (3-D), one set per field
     T q0[NF], q1[NF], q2[NF], dmq[NF], qI[NF], Fzp[NF];
     Parab<T> pprev[NF];
@@ -550,15 +624,15 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
         if (need_vel) {
             int fz = 0;
             const int az = NDIM == 3 ? map_index(vpl, nz, gp.bc_lo[2], gp.bc_hi[2], fz) : 0;
-            for (int li = tid; li < VS; li += NT) {
-                const int ix = li % VW, iy = li / VW;
-                int fx, fy = 0;
-                const int ax = map_index(x0 + ix - 1, nx, gp.bc_lo[0], gp.bc_hi[0], fx);
-                const int ay = NDIM >= 2 ? map_index(y0 + iy - 1, ny, gp.bc_lo[1], gp.bc_hi[1], fy) : 0;
-                const long long c = ((long long)az * ny + ay) * nx + ax;
-                const T rho = Wst[c];
-                T mxv = Wst[N + c];
-                if (fx) mxv = -mxv;
+#pragma unroll
+            for (int r = 0; r < RV; r++) {
+                if (vcode[r] < 0) continue;
+                const int li = tid + r * NT;
+                const unsigned fl = flips >> (2 * (RC + r));
+                const int c = az * plane + vcode[r];
+                const T rho = Wf[0][c];
+                T mxv = Wf[1][c];
+                if (fl & 1) mxv = -mxv;
 #ifdef PPML_EXACT
                 s_vx[slot][li] = mxv / rho;
 #else
@@ -566,8 +640,8 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                 s_vx[slot][li] = mxv * ir;
 #endif
                 if constexpr (NDIM >= 2) {
-                    T myv = Wst[2 * N + c];
-                    if (fy) myv = -myv;
+                    T myv = Wf[2][c];
+                    if (fl & 2) myv = -myv;
 #ifdef PPML_EXACT
                     s_vy[slot][li] = myv / rho;
 #else
@@ -575,7 +649,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
 #endif
                 }
                 if constexpr (NDIM == 3) {
-                    T mzv = Wst[3 * N + c];
+                    T mzv = Wf[3][c];
                     if (fz) mzv = -mzv;
 #ifdef PPML_EXACT
                     s_vz[zslot][li] = mzv / rho;
@@ -590,11 +664,11 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
             // own-column loads of plane m for every field: z parabola of cell m-2
             int fz;
             const int mz = map_index(m, nz, gp.bc_lo[2], gp.bc_hi[2], fz);
-            const long long c = ((long long)mz * ny + cy_) * nx + cx_;
+            const int c = mz * plane + own_off;
             Parab<T> pnew[NF];
 #pragma unroll
             for (int f = 0; f < NF; f++) {
-                T v = Wst[f * N + c];
+                T v = Wf[f][c];
                 if (f == 3 && fz) v = -v;
                 q0[f] = q1[f];
                 q1[f] = q2[f];
@@ -638,77 +712,35 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
         // ---- x / y directions of plane k, G fields per pass ----
         T acc[NF];
         T own[NF];  // U^{n+1/2} of the thread's own cell, read from the tiles
+        constexpr int NJF = (NXI + NYI + NT - 1) / NT;
+        T vhr[NJF];  // interface velocities of this thread's flux jobs
+        // velocity ring slots of planes k-1, k, k+1
+        const int sm = NDIM == 3 ? ((k - 1) % 3 + 3) % 3 : 0;
+        const int s0 = NDIM == 3 ? (k % 3 + 3) % 3 : 0;
+        const int sp = NDIM == 3 ? ((k + 1) % 3 + 3) % 3 : 0;
+        (void)sm;
+        (void)s0;
+        (void)sp;
 #pragma unroll
         for (int pass = 0; pass < NPASS; pass++) {
             const int f0 = pass * G;
             // cross tiles of the pass's fields
-            for (int li = tid; li < PS; li += NT) {
-                const int ix = li % PW, iy = li / PW;
-                const int dx = ix - HX, dy = iy - HY;
-                const bool cross = (dy >= 0 && dy < TY) || (dx >= 0 && dx < TX);
-                if (!cross) continue;
-                int fx, fy = 0;
-                const int ax = map_index(x0 + dx, nx, gp.bc_lo[0], gp.bc_hi[0], fx);
-                const int ay = NDIM >= 2 ? map_index(y0 + dy, ny, gp.bc_lo[1], gp.bc_hi[1], fy) : 0;
-                const long long c = ((long long)k * ny + ay) * nx + ax;
+#pragma unroll
+            for (int r = 0; r < RC; r++) {
+                if (ccode[r] < 0) continue;
+                const int li = tid + r * NT;
+                const unsigned fl = flips >> (2 * r);
+                const int c = k * plane + ccode[r];
 #pragma unroll
                 for (int g = 0; g < G; g++) {
                     const int f = f0 + g;
                     if (f >= NF) break;
-                    T v = Wst[f * N + c];
-                    if ((f == 1 && fx) || (NDIM >= 2 && f == 2 && fy)) v = -v;
+                    T v = Wf[f][c];
+                    if ((f == 1 && (fl & 1)) || (NDIM >= 2 && f == 2 && (fl & 2))) v = -v;
                     s_f[g][li] = v;
                 }
             }
             __syncthreads();
-            if (pass == 0) {
-                // interface velocities of the x and y interfaces of the plane
-                const int sm = NDIM == 3 ? ((k - 1) % 3 + 3) % 3 : 0;
-                const int s0 = NDIM == 3 ? (k % 3 + 3) % 3 : 0;
-                const int sp = NDIM == 3 ? ((k + 1) % 3 + 3) % 3 : 0;
-                for (int j = tid; j < NXI + NYI; j += NT) {
-                    if (j < NXI) {
-                        const int ix = j % (TX + 1), cy = j / (TX + 1);
-                        T vt[2];
-#pragma unroll
-                        for (int u = 0; u < 2; u++) {
-                            const int l = (cy + 1) * VW + ix + u;  // tile-rel x = ix-1+u
-                            if constexpr (NDIM == 3) {
-                                const T *A = s_vx[sm], *B = s_vx[s0], *C = s_vx[sp];
-                                // transverse axes y (first) and z (second)
-                                vt[u] = tmpl9(C[l + VW], A[l + VW], C[l - VW], A[l - VW], B[l + VW], B[l - VW], C[l],
-                                              A[l], B[l]);
-                            } else if constexpr (NDIM == 2) {
-                                const T *B = s_vx[0];
-                                vt[u] = tmpl3(B[l + VW], B[l - VW], B[l]);
-                            } else {
-                                vt[u] = s_vx[0][ix + u];
-                            }
-                        }
-                        const int la = (cy + HY) * PW + ix - 1 + HX;
-                        xvh[j] = interface_velocity(vt[0], dsqrt(s_f[0][la]), vt[1], dsqrt(s_f[0][la + 1]));
-                    } else if constexpr (NDIM >= 2) {
-                        const int jj = j - NXI;
-                        const int cx = jj % TX, iy = jj / TX;
-                        T vt[2];
-#pragma unroll
-                        for (int u = 0; u < 2; u++) {
-                            const int l = (iy + u) * VW + cx + 1;  // tile-rel y = iy-1+u
-                            if constexpr (NDIM == 3) {
-                                const T *A = s_vy[sm], *B = s_vy[s0], *C = s_vy[sp];
-                                // transverse axes x (first) and z (second)
-                                vt[u] = tmpl9(C[l + 1], A[l + 1], C[l - 1], A[l - 1], B[l + 1], B[l - 1], C[l], A[l],
-                                              B[l]);
-                            } else {
-                                const T *B = s_vy[0];
-                                vt[u] = tmpl3(B[l + 1], B[l - 1], B[l]);
-                            }
-                        }
-                        const int la = (iy - 1 + HY) * PW + cx + HX;
-                        yvh[jj] = interface_velocity(vt[0], dsqrt(s_f[0][la]), vt[1], dsqrt(s_f[0][la + PW]));
-                    }
-                }
-            }
             // interface values (Appendix step 1) at every face of the tile
             for (int j = tid; j < NXQ + NYQ; j += NT) {
                 if (j < NXQ) {
@@ -740,14 +772,35 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
             // upwind fluxes: only the upwind cell's parabola is needed.  They
             // are kept in registers until every job has read the face values,
             // then stored over the face arrays.
-            constexpr int NJF = (NXI + NYI + NT - 1) / NT;
             T Fr[NJF][G];
 #pragma unroll
             for (int r = 0; r < NJF; r++) {
                 const int j = tid + r * NT;
                 if (j < NXI) {
                     const int ix = j % (TX + 1), cy = j / (TX + 1);
-                    const T vh = xvh[j];
+                    if (pass == 0) {
+                        // interface velocity: 9-point transverse velocity of
+                        // both cells, weighted by sqrt(rho) (Sec. 2.3)
+                        T vt[2];
+#pragma unroll
+                        for (int u = 0; u < 2; u++) {
+                            const int l = (cy + 1) * VW + ix + u;  // tile-rel x = ix-1+u
+                            if constexpr (NDIM == 3) {
+                                const T *A = s_vx[sm], *B = s_vx[s0], *C = s_vx[sp];
+                                // transverse axes y (first) and z (second)
+                                vt[u] = tmpl9(C[l + VW], A[l + VW], C[l - VW], A[l - VW], B[l + VW], B[l - VW], C[l],
+                                              A[l], B[l]);
+                            } else if constexpr (NDIM == 2) {
+                                const T *B = s_vx[0];
+                                vt[u] = tmpl3(B[l + VW], B[l - VW], B[l]);
+                            } else {
+                                vt[u] = s_vx[0][ix + u];
+                            }
+                        }
+                        const int la = (cy + HY) * PW + ix - 1 + HX;
+                        vhr[r] = interface_velocity(vt[0], dsqrt(s_f[0][la]), vt[1], dsqrt(s_f[0][la + 1]));
+                    }
+                    const T vh = vhr[r];
                     const bool left = vh >= T(0);
                     const int u = left ? ix - 1 : ix;             // tile-rel upwind cell
                     const int lq = (cy + HY) * PW + u + HX;       // its value
@@ -767,7 +820,25 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                 } else if (NDIM >= 2 && j < NXI + NYI) {
                     const int jj = j - NXI;
                     const int cx = jj % TX, iy = jj / TX;
-                    const T vh = yvh[jj];
+                    if (pass == 0) {
+                        T vt[2];
+#pragma unroll
+                        for (int u = 0; u < 2; u++) {
+                            const int l = (iy + u) * VW + cx + 1;  // tile-rel y = iy-1+u
+                            if constexpr (NDIM == 3) {
+                                const T *A = s_vy[sm], *B = s_vy[s0], *C = s_vy[sp];
+                                // transverse axes x (first) and z (second)
+                                vt[u] = tmpl9(C[l + 1], A[l + 1], C[l - 1], A[l - 1], B[l + 1], B[l - 1], C[l], A[l],
+                                              B[l]);
+                            } else {
+                                const T *B = s_vy[0];
+                                vt[u] = tmpl3(B[l + 1], B[l - 1], B[l]);
+                            }
+                        }
+                        const int la = (iy - 1 + HY) * PW + cx + HX;
+                        vhr[r] = interface_velocity(vt[0], dsqrt(s_f[0][la]), vt[1], dsqrt(s_f[0][la + PW]));
+                    }
+                    const T vh = vhr[r];
                     const bool left = vh >= T(0);
                     const int u = left ? iy - 1 : iy;
                     const int lq = (u + HY) * PW + cx + HX;
@@ -814,7 +885,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
         }
 
         if (valid) {
-            const long long c = ((long long)k * ny + gy) * nx + gx;
+            const int c = k * plane + gy * nx + gx;
             T fn[NF];
 #pragma unroll
             for (int f = 0; f < NF; f++) fn[f] = own[f] - tau * acc[f];
@@ -845,7 +916,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                 if (d > 0.0) fn[NDIM + 2] = (T)d;
             }
 #pragma unroll
-            for (int f = 0; f < NF; f++) U[f * N + c] = fn[f];
+            for (int f = 0; f < NF; f++) U[(size_t)f * (size_t)N + c] = fn[f];
             T v, cs;
             cell_speeds<T, NDIM>(fn[0], fn[1], NDIM >= 2 ? fn[2] : T(0), NDIM >= 3 ? fn[3] : T(0), fn[NDIM + 2], gam,
                                  gm1, v, cs);
