@@ -116,7 +116,8 @@ ScratchLayout layout(const ppml_desc *d)
 
 struct ppml_grid {
     ppml_desc d;
-    GridParams gp;
+    GridParams gp;         // batch launches and the per-cell kernels
+    GridParams gpE, gpL;   // solo launches of the two stage kernels (own z chunks)
     hipStream_t stream;
     int device;
     void *state;
@@ -149,8 +150,8 @@ template <typename T> void launch_step(ppml_grid *g, hipEvent_t *ev)
     const T *U = (const T *)g->state;
     T *Us = (T *)g->state;
     T *W = (T *)g->half;
-    const GridParams &gp = g->gp;
-    const int nb = gp.tiles[0] * gp.tiles[1] * gp.tiles[2];
+    const GridParams &gp = g->gpE;
+    int nb = gp.tiles[0] * gp.tiles[1] * gp.tiles[2];
     if (ev) (void)hipEventRecord(ev[0], g->stream);
     switch (g->d.ndim) {
     case 1: k_euler<T, 1, T1X, 1><<<nb, T1X, 0, g->stream>>>(U, W, gp, g->ctrl); break;
@@ -158,10 +159,12 @@ template <typename T> void launch_step(ppml_grid *g, hipEvent_t *ev)
     default: k_euler<T, 3, T3X, T3Y><<<nb, T3X * T3Y, 0, g->stream>>>(U, W, gp, g->ctrl); break;
     }
     if (ev) (void)hipEventRecord(ev[1], g->stream);
+    const GridParams &gl = g->gpL;
+    nb = gl.tiles[0] * gl.tiles[1] * gl.tiles[2];
     switch (g->d.ndim) {
-    case 1: k_lagr<T, 1, T1X, 1, LG<T>::g><<<nb, T1X, 0, g->stream>>>(W, Us, gp, g->ctrl); break;
-    case 2: k_lagr<T, 2, T2X, T2Y, LG<T>::g><<<nb, T2X * T2Y, 0, g->stream>>>(W, Us, gp, g->ctrl); break;
-    default: k_lagr<T, 3, T3X, T3Y, LG<T>::g><<<nb, T3X * T3Y, 0, g->stream>>>(W, Us, gp, g->ctrl); break;
+    case 1: k_lagr<T, 1, T1X, 1, LG<T>::g><<<nb, T1X, 0, g->stream>>>(W, Us, gl, g->ctrl); break;
+    case 2: k_lagr<T, 2, T2X, T2Y, LG<T>::g><<<nb, T2X * T2Y, 0, g->stream>>>(W, Us, gl, g->ctrl); break;
+    default: k_lagr<T, 3, T3X, T3Y, LG<T>::g><<<nb, T3X * T3Y, 0, g->stream>>>(W, Us, gl, g->ctrl); break;
     }
     if (ev) (void)hipEventRecord(ev[2], g->stream);
 }
@@ -224,6 +227,51 @@ bool all_finite(const double *a, long long n)
     for (long long i = 0; i < n; i++)
         if (!std::isfinite(a[i])) return false;
     return true;
+}
+
+// Number of z chunks of a 3-D stage launch.  A work group streams cz planes
+// after `warm` planes of pipeline start-up (in units of a full plane); the
+// launch runs in ceil(groups / slots) rounds of resident work groups, so the
+// time is modelled as rounds * (cz + warm) and minimised over the chunk count.
+int choose_chunks(long long tiles_xy, int nz, long long slots, double warm)
+{
+    if (slots < 1) slots = 1;
+    int best = 1;
+    double best_cost = 1e300;
+    for (int c = 1; c <= nz; c++) {
+        const int cz = (nz + c - 1) / c;
+        if ((long long)(c - 1) * cz >= nz) continue;  // same chunks as a smaller count
+        const long long groups = tiles_xy * c;
+        if (groups > (1ll << 30)) break;
+        const double rounds = (double)((groups + slots - 1) / slots);
+        const double cost = rounds * (cz + warm);
+        if (cost < best_cost * (1.0 - 1e-9)) {
+            best_cost = cost;
+            best = c;
+        }
+    }
+    return best;
+}
+
+template <typename T> void stage_slots(int device, long long &slots_e, long long &slots_l)
+{
+    int cus = 0, be = 0, bl = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&be, k_euler<T, 3, T3X, T3Y>, T3X * T3Y, 0) != hipSuccess) be = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bl, k_lagr<T, 3, T3X, T3Y, LG<T>::g>, T3X * T3Y, 0) !=
+        hipSuccess)
+        bl = 0;
+    (void)hipGetLastError();
+    if (cus < 1) cus = 256;
+    slots_e = (long long)cus * (be > 0 ? be : 2);
+    slots_l = (long long)cus * (bl > 0 ? bl : 2);
+}
+
+void set_chunks(GridParams &gp, int chunks)
+{
+    const int nz = gp.n[2];
+    gp.cz = (nz + chunks - 1) / chunks;
+    gp.tiles[2] = (nz + gp.cz - 1) / gp.cz;
 }
 
 }  // namespace
@@ -301,6 +349,19 @@ int ppml_create(const ppml_desc *d, void *state_dev, void *scratch_dev, void *hi
         while (cz > 16 && tiles * ((gp.n[2] + cz - 1) / cz) < 2048) cz = (cz + 1) / 2;
         gp.cz = cz;
         gp.tiles[2] = (gp.n[2] + cz - 1) / cz;
+    }
+    g->gpE = gp;
+    g->gpL = gp;
+    if (d->ndim == 3) {
+        // solo launches: z chunks fitted to the resident work groups of each
+        // stage kernel (start-up cost: 3 z-only planes in the Eulerian
+        // kernel, 6 in the Lagrangian kernel)
+        long long se, sl;
+        if (d->prec == PPML_FP64) stage_slots<double>(g->device, se, sl);
+        else stage_slots<float>(g->device, se, sl);
+        const long long txy = (long long)gp.tiles[0] * gp.tiles[1];
+        set_chunks(g->gpE, choose_chunks(txy, gp.n[2], se, 1.5));
+        set_chunks(g->gpL, choose_chunks(txy, gp.n[2], sl, 3.0));
     }
     g->has_state = false;
     g->in_batch = false;

@@ -23,6 +23,12 @@ namespace ppml {
 
 template <typename T> __device__ __forceinline__ T ldg(const T *p) { return __builtin_nontemporal_load(p); }
 
+// s_waitcnt operand that waits for every outstanding vector-memory operation
+// of the wave (vmcnt = 0) and leaves the export and LDS/scalar counters
+// unconstrained (gfx9 encoding: vmcnt[3:0], expcnt[6:4], lgkmcnt[11:8],
+// vmcnt[15:14]).
+constexpr int VMCNT0 = 0x0F70;
+
 // ---------------------------------------------------------------------------
 // State initialisation and conversion kernels
 // ---------------------------------------------------------------------------
@@ -259,6 +265,7 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
         Wf[f] = Wst + (size_t)f * (size_t)N;
     }
     const int plane = nx * ny;
+    const int own_off = cy_ * nx + cx_;
 
     // Cross-tile cells this thread stages on every plane: (y, x) offset of
     // the boundary-mapped source cell (-1 where nothing is loaded) and the
@@ -336,16 +343,26 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
         }
 
         // ---- x / y directions of plane k from LDS ----
+        // every round's loads first, so that the tile costs one memory
+        // latency; lanes without a cross cell load their own cell
+        T xr[RC][NDIM + 2];  // rho, m_x, (m_y), rho*eps
+#pragma unroll
+        for (int r = 0; r < RC; r++) {
+            const int c = k * plane + (ccode[r] >= 0 ? ccode[r] : own_off);
+            xr[r][0] = Uf[0][c];
+            xr[r][1] = Uf[1][c];
+            if constexpr (NDIM >= 2) xr[r][2] = Uf[2][c];
+            xr[r][NDIM + 1] = Uf[2 + NDIM][c];
+        }
 #pragma unroll
         for (int r = 0; r < RC; r++) {
             if (ccode[r] < 0) continue;
             const int li = tid + r * NT;
             const unsigned fl = flips >> (2 * r);
-            const int c = k * plane + ccode[r];
-            const T rho = Uf[0][c];
-            T mxv = Uf[1][c];
+            const T rho = xr[r][0];
+            T mxv = xr[r][1];
             if (fl & 1) mxv = -mxv;
-            const T e = Uf[2 + NDIM][c];
+            const T e = xr[r][NDIM + 1];
 #ifdef PPML_EXACT
             s_vx[li] = mxv / rho;
 #else
@@ -353,7 +370,7 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
             s_vx[li] = mxv * ir;
 #endif
             if constexpr (NDIM >= 2) {
-                T myv = Uf[2][c];
+                T myv = xr[r][2];
                 if (fl & 2) myv = -myv;
 #ifdef PPML_EXACT
                 s_vy[li] = myv / rho;
@@ -500,7 +517,12 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
     constexpr int VS = VW * VH;
     constexpr int NR = NDIM == 3 ? 3 : 1;
 
-    __shared__ T s_f[G][PS];
+    // FP32 3-D: the cross tile of plane k+1 travels from memory straight to
+    // LDS (one transfer per lane and field) while plane k is computed, into
+    // the second of two tile buffers
+    constexpr bool PIPE = sizeof(T) == 4 && NDIM == 3 && G >= NF;
+    constexpr int NBUF = PIPE ? 2 : 1;
+    __shared__ T s_f[NBUF][G][PS];
     __shared__ T s_qx[G][NXQ];
     __shared__ T s_qy[G][NYQ > 0 ? NYQ : 1];
     // fluxes reuse the interface-value arrays once those are consumed
@@ -610,11 +632,41 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
 
     const int m_beg = NDIM == 3 ? z0 - 3 : 0;
     const int m_end = NDIM == 3 ? z1 + 3 : 1;
+
+    // cross tile of plane kk, every field, from memory into the LDS buffer of
+    // plane kk: each wave fills 64 consecutive tile slots per field, lanes
+    // without a cross cell do not transfer
+    auto dma_cross = [&](int kk) {
+        T (*dst)[PS] = s_f[kk & 1];
+#pragma unroll
+        for (int r = 0; r < RC; r++) {
+            if (ccode[r] < 0) continue;
+            const int c = kk * plane + ccode[r];
+            const int wbase = r * NT + (tid & ~63);
+#pragma unroll
+            for (int f = 0; f < NF; f++)
+                __builtin_amdgcn_global_load_lds((const void *)(Wf[f] + c),
+                                                 (__attribute__((address_space(3))) void *)&dst[f][wbase], 4, 0, 0);
+        }
+    };
+    if constexpr (PIPE) dma_cross(z0);
+
     for (int m = m_beg; m < m_end; ++m) {
         const int k = NDIM == 3 ? m - 3 : 0;
         T DFz[NF];
 #pragma unroll
         for (int f = 0; f < NF; f++) DFz[f] = T(0);
+
+        // own column, plane m, every field (3-D), loaded together with the
+        // velocity tile below so that the plane costs one memory latency
+        T ov[NF];
+        int fzo = 0;
+        if constexpr (NDIM == 3) {
+            const int mz = map_index(m, nz, gp.bc_lo[2], gp.bc_hi[2], fzo);
+            const int c = mz * plane + own_off;
+#pragma unroll
+            for (int f = 0; f < NF; f++) ov[f] = Wf[f][c];
+        }
 
         // velocity plane needed by this iteration (3-D: plane m-2; else plane 0)
         const int vpl = NDIM == 3 ? m - 2 : 0;
@@ -624,14 +676,22 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
         if (need_vel) {
             int fz = 0;
             const int az = NDIM == 3 ? map_index(vpl, nz, gp.bc_lo[2], gp.bc_hi[2], fz) : 0;
+            // every round's loads first (lanes without a tile cell load their
+            // own cell), then the velocities
+            T vr[RV][NDIM + 1];
+#pragma unroll
+            for (int r = 0; r < RV; r++) {
+                const int c = az * plane + (vcode[r] >= 0 ? vcode[r] : own_off);
+#pragma unroll
+                for (int a = 0; a <= NDIM; a++) vr[r][a] = Wf[a][c];
+            }
 #pragma unroll
             for (int r = 0; r < RV; r++) {
                 if (vcode[r] < 0) continue;
                 const int li = tid + r * NT;
                 const unsigned fl = flips >> (2 * (RC + r));
-                const int c = az * plane + vcode[r];
-                const T rho = Wf[0][c];
-                T mxv = Wf[1][c];
+                const T rho = vr[r][0];
+                T mxv = vr[r][1];
                 if (fl & 1) mxv = -mxv;
 #ifdef PPML_EXACT
                 s_vx[slot][li] = mxv / rho;
@@ -640,7 +700,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                 s_vx[slot][li] = mxv * ir;
 #endif
                 if constexpr (NDIM >= 2) {
-                    T myv = Wf[2][c];
+                    T myv = vr[r][2];
                     if (fl & 2) myv = -myv;
 #ifdef PPML_EXACT
                     s_vy[slot][li] = myv / rho;
@@ -649,7 +709,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
 #endif
                 }
                 if constexpr (NDIM == 3) {
-                    T mzv = Wf[3][c];
+                    T mzv = vr[r][3];
                     if (fz) mzv = -mzv;
 #ifdef PPML_EXACT
                     s_vz[zslot][li] = mzv / rho;
@@ -661,15 +721,12 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
         }
 
         if constexpr (NDIM == 3) {
-            // own-column loads of plane m for every field: z parabola of cell m-2
-            int fz;
-            const int mz = map_index(m, nz, gp.bc_lo[2], gp.bc_hi[2], fz);
-            const int c = mz * plane + own_off;
+            // own column, plane m, every field: z parabola of cell m-2
             Parab<T> pnew[NF];
 #pragma unroll
             for (int f = 0; f < NF; f++) {
-                T v = Wf[f][c];
-                if (f == 3 && fz) v = -v;
+                T v = ov[f];
+                if (f == 3 && fzo) v = -v;
                 q0[f] = q1[f];
                 q1[f] = q2[f];
                 q2[f] = v;
@@ -710,6 +767,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
         }
 
         // ---- x / y directions of plane k, G fields per pass ----
+        T (*sf)[PS] = s_f[PIPE ? (k & 1) : 0];  // cross tile of plane k
         T acc[NF];
         T own[NF];  // U^{n+1/2} of the thread's own cell, read from the tiles
         constexpr int NJF = (NXI + NYI + NT - 1) / NT;
@@ -724,20 +782,37 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
 #pragma unroll
         for (int pass = 0; pass < NPASS; pass++) {
             const int f0 = pass * G;
-            // cross tiles of the pass's fields
+            if constexpr (PIPE) {
+                // the cross tile of plane k was sent to LDS one plane ago:
+                // wait for this wave's transfers, then mirror the normal
+                // momenta at reflecting faces
+                __builtin_amdgcn_s_waitcnt(VMCNT0);
+                if (flips) {
 #pragma unroll
-            for (int r = 0; r < RC; r++) {
-                if (ccode[r] < 0) continue;
-                const int li = tid + r * NT;
-                const unsigned fl = flips >> (2 * r);
-                const int c = k * plane + ccode[r];
+                    for (int r = 0; r < RC; r++) {
+                        if (ccode[r] < 0) continue;
+                        const int li = tid + r * NT;
+                        const unsigned fl = flips >> (2 * r);
+                        if (fl & 1) sf[1][li] = -sf[1][li];
+                        if (NDIM >= 2 && (fl & 2)) sf[2][li] = -sf[2][li];
+                    }
+                }
+            } else {
+                // cross tiles of the pass's fields
 #pragma unroll
-                for (int g = 0; g < G; g++) {
-                    const int f = f0 + g;
-                    if (f >= NF) break;
-                    T v = Wf[f][c];
-                    if ((f == 1 && (fl & 1)) || (NDIM >= 2 && f == 2 && (fl & 2))) v = -v;
-                    s_f[g][li] = v;
+                for (int r = 0; r < RC; r++) {
+                    if (ccode[r] < 0) continue;
+                    const int li = tid + r * NT;
+                    const unsigned fl = flips >> (2 * r);
+                    const int c = k * plane + ccode[r];
+#pragma unroll
+                    for (int g = 0; g < G; g++) {
+                        const int f = f0 + g;
+                        if (f >= NF) break;
+                        T v = Wf[f][c];
+                        if ((f == 1 && (fl & 1)) || (NDIM >= 2 && f == 2 && (fl & 2))) v = -v;
+                        sf[g][li] = v;
+                    }
                 }
             }
             __syncthreads();
@@ -749,7 +824,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
 #pragma unroll
                     for (int g = 0; g < G; g++) {
                         if (f0 + g >= NF) break;
-                        const T *q = s_f[g];
+                        const T *q = sf[g];
                         const T da = limited_slope(q[l], q[l + 1], q[l + 2]);
                         const T db = limited_slope(q[l + 1], q[l + 2], q[l + 3]);
                         s_qx[g][j] = interface_value(q[l + 1], q[l + 2], da, db);
@@ -761,7 +836,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
 #pragma unroll
                     for (int g = 0; g < G; g++) {
                         if (f0 + g >= NF) break;
-                        const T *q = s_f[g];
+                        const T *q = sf[g];
                         const T da = limited_slope(q[l], q[l + PW], q[l + 2 * PW]);
                         const T db = limited_slope(q[l + PW], q[l + 2 * PW], q[l + 3 * PW]);
                         s_qy[g][jj] = interface_value(q[l + PW], q[l + 2 * PW], da, db);
@@ -798,7 +873,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                             }
                         }
                         const int la = (cy + HY) * PW + ix - 1 + HX;
-                        vhr[r] = interface_velocity(vt[0], dsqrt(s_f[0][la]), vt[1], dsqrt(s_f[0][la + 1]));
+                        vhr[r] = interface_velocity(vt[0], dsqrt(sf[0][la]), vt[1], dsqrt(sf[0][la + 1]));
                     }
                     const T vh = vhr[r];
                     const bool left = vh >= T(0);
@@ -813,7 +888,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
 #pragma unroll
                     for (int g = 0; g < G; g++) {
                         if (f0 + g >= NF) break;
-                        const Parab<T> p = profile(gp.first_order, s_f[g][lq], s_qx[g][lf], s_qx[g][lf + 1]);
+                        const Parab<T> p = profile(gp.first_order, sf[g][lq], s_qx[g][lf], s_qx[g][lf + 1]);
                         const T fs = left ? avg_left(p.L, p.R, p.Q6, z) : avg_right(p.L, p.R, p.Q6, z);
                         Fr[r][g] = vh * fs;
                     }
@@ -836,7 +911,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                             }
                         }
                         const int la = (iy - 1 + HY) * PW + cx + HX;
-                        vhr[r] = interface_velocity(vt[0], dsqrt(s_f[0][la]), vt[1], dsqrt(s_f[0][la + PW]));
+                        vhr[r] = interface_velocity(vt[0], dsqrt(sf[0][la]), vt[1], dsqrt(sf[0][la + PW]));
                     }
                     const T vh = vhr[r];
                     const bool left = vh >= T(0);
@@ -851,7 +926,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
 #pragma unroll
                     for (int g = 0; g < G; g++) {
                         if (f0 + g >= NF) break;
-                        const Parab<T> p = profile(gp.first_order, s_f[g][lq], s_qy[g][lf], s_qy[g][lf + TX]);
+                        const Parab<T> p = profile(gp.first_order, sf[g][lq], s_qy[g][lf], s_qy[g][lf + TX]);
                         const T fs = left ? avg_left(p.L, p.R, p.Q6, z) : avg_right(p.L, p.R, p.Q6, z);
                         Fr[r][g] = vh * fs;
                     }
@@ -876,13 +951,20 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
             for (int g = 0; g < G; g++) {
                 const int f = f0 + g;
                 if (f >= NF) break;
-                own[f] = s_f[g][(ty + HY) * PW + tx + HX];
+                own[f] = sf[g][(ty + HY) * PW + tx + HX];
                 T a = PPML_DIV(s_Fx[g][ty * (TX + 1) + tx + 1] - s_Fx[g][ty * (TX + 1) + tx], hx, ihx);
                 if constexpr (NDIM >= 2) a = a + PPML_DIV(s_Fy[g][(ty + 1) * TX + tx] - s_Fy[g][ty * TX + tx], hy, ihy);
                 if constexpr (NDIM == 3) a = a + DFz[f];
                 acc[f] = a;
             }
         }
+        // This wave's last read of a cross tile in this plane is done, and
+        // every wave is past the previous plane: the previous plane's buffer
+        // takes the next plane's cross tile, whose transfer overlaps the
+        // update below and the next plane's z arithmetic.  (Issued after the
+        // last tile read, so that no LDS read of this plane waits for it.)
+        if constexpr (PIPE)
+            if (k + 1 < z1) dma_cross(k + 1);
 
         if (valid) {
             const int c = k * plane + gy * nx + gx;
@@ -930,8 +1012,13 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
     publish_max(ctrl, sl ^ 1, vmax, cmax);
 }
 
+// Waves per SIMD the register allocator aims for in the Lagrangian kernel:
+// three 4-wave work groups per CU (<= 168 VGPRs) for the FP32 3-D kernel,
+// whose LDS tiles also fit three times; the compiler's choice otherwise.
+template <typename T, int NDIM> constexpr int lagr_waves() { return (sizeof(T) == 4 && NDIM == 3) ? 3 : 1; }
+
 template <typename T, int NDIM, int TX, int TY, int G>
-__global__ __launch_bounds__(TX *TY) void k_lagr(const T *__restrict__ Wst, T *__restrict__ U, GridParams gp,
+__global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(lagr_waves<T, NDIM>()))) void k_lagr(const T *__restrict__ Wst, T *__restrict__ U, GridParams gp,
                                                   Ctrl *ctrl)
 {
     int bx, by, bz;
@@ -977,7 +1064,7 @@ __global__ __launch_bounds__(TX *TY) void k_euler_batch(const BatchEntry *__rest
 }
 
 template <typename T, int NDIM, int TX, int TY, int G>
-__global__ __launch_bounds__(TX *TY) void k_lagr_batch(const BatchEntry *__restrict__ ents, int ne)
+__global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(lagr_waves<T, NDIM>()))) void k_lagr_batch(const BatchEntry *__restrict__ ents, int ne)
 {
     const BatchEntry *e = ents + batch_entry(ents, ne, blockIdx.x);
     const int L = blockIdx.x - e->tile0;

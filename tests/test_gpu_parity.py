@@ -162,9 +162,21 @@ def test_fp64_multid(name, prob):
     _assert_close(g, o, prob.ndim, 1e-12, name)
 
 
-@pytest.mark.parametrize("name,prob", CASES[:1] + CASES[5:6] + CASES[8:9], ids=["2d", "3d", "3d_logpot"])
+def _mixed_bc_3d(prob):
+    prob.bc = [("reflect", "outflow"), ("outflow", "reflect"), ("reflect", "reflect")]
+    return prob
+
+
+FP32_CASES = CASES[:1] + CASES[5:9] + [
+    # several tiles along x and y, every boundary kind on some face
+    ("smooth3d_mixed_tiles", _mixed_bc_3d(W.random_smooth(3, (70, 20, 26), seed=10))),
+]
+
+
+@pytest.mark.parametrize("name,prob", FP32_CASES, ids=[c[0] for c in FP32_CASES])
 def test_fp32_multid(name, prob):
-    """FP32 state, driven with the oracle's time steps."""
+    """FP32 state, driven with the oracle's time steps (the FP32 3-D path
+    stages its tiles through asynchronous memory-to-LDS transfers)."""
     o = make_oracle(prob)
     taus = o.run(12)
     g = _grid(prob, prec="fp32")
