@@ -83,12 +83,12 @@ def algorithmic_bytes_per_zone(kernel: str, ndim: int, width: int) -> int:
     return (2 * F - 1) * width if kernel == "euler" else 2 * F * width
 
 
-def run_precision(prob, prec, steps, warmup):
+def run_precision(prob, prec, steps, warmup, tile=0):
     import torch
 
     from paper_1607_01105_amd.ppml import Grid
 
-    g = Grid.from_problem(prob, prec=prec, device="cuda:0")
+    g = Grid.from_problem(prob, prec=prec, device="cuda:0", tile=tile)
     if warmup > 0:
         g.step(warmup)
         g.sync()
@@ -114,21 +114,25 @@ def run_precision(prob, prec, steps, warmup):
                 rho=rho, totals=tot)
 
 
-def run_batched(seed=0, steps=200):
+def run_batched(seed=0, steps=200, tune=True):
     """Batched configuration: 128 1-D Riemann problems (64-4096 cells) and
     128 2-D periodic boxes (sides 32-256), FP32, 200 steps each.  Plain
     per-grid launches against one batched launch sequence replayed from a HIP
-    graph; the two give the same bits for every grid."""
+    graph; the two give the same bits for every grid.  Both use the tile
+    shape per dimensionality that the autotuner picks for the batch."""
     import numpy as np
     import torch
 
+    from paper_1607_01105_amd import autotune
     from paper_1607_01105_amd import workloads as W
     from paper_1607_01105_amd.ppml import Batch, Grid
 
     probs = W.batch_mix(seed, steps=steps)
     cells = sum(p.cells for p in probs)
+    tuned = autotune.tune_batch(probs, prec="fp32", log=_log) if tune else {}
+    tiles = {nd: r["tile"] for nd, r in tuned.items()}
     stream = torch.cuda.Stream()
-    plain = [Grid.from_problem(p, prec="fp32", stream=stream) for p in probs]
+    plain = [Grid.from_problem(p, prec="fp32", stream=stream, tile=tiles.get(p.ndim, 0)) for p in probs]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for g in plain:
@@ -137,6 +141,8 @@ def run_batched(seed=0, steps=200):
         g.sync()
     t_plain = time.perf_counter() - t0
     b = Batch(len(probs))
+    for nd, v in tiles.items():
+        b.set_tile(nd, v)
     slots = [b.admit(b.new_grid(p, prec="fp32")) for p in probs]
     t0 = time.perf_counter()
     b.step(steps, graph=True)  # records the graph, then replays it
@@ -154,7 +160,8 @@ def run_batched(seed=0, steps=200):
             "grids": len(probs), "cells": cells, "steps": steps,
             "plain_zone_updates_per_s": cells * steps / t_plain, "plain_s": t_plain,
             "batched_graph_zone_updates_per_s": cells * steps / t_batch, "batched_s": t_batch,
-            "batched_first_call_s": t_first, "speedup": t_plain / t_batch, "bitwise_equal_to_plain": bool(same)}
+            "batched_first_call_s": t_first, "speedup": t_plain / t_batch, "bitwise_equal_to_plain": bool(same),
+            "tile_shapes": {str(nd): list(r["shape"]) for nd, r in tuned.items()}}
 
 
 def run_served(n_requests=60, load=0.5, seed=0, budget_gib=4.0, round_steps=50, capacity_zu_per_s=None):
@@ -172,14 +179,24 @@ def run_served(n_requests=60, load=0.5, seed=0, budget_gib=4.0, round_steps=50, 
     cap_rps = capacity_zu_per_s / mean_zu
     rate = load * cap_rps
     trace = W.served_trace(seed, n_requests, rate)
-    srv = Server(budget_bytes=int(budget_gib * (1 << 30)), capacity=256, prec="fp32", round_steps=round_steps)
+    # tile shapes for the mix, tuned on a few requests of another seed
+    from paper_1607_01105_amd import autotune
+
+    sample = [r.problem() for r in W.served_trace(seed + 1, 6, 1.0, n2_range=(64, 256), n3_range=(64, 96))]
+    tiles = {nd: r["tile"] for nd, r in autotune.tune_batch(sample, prec="fp32", steps=4, log=_log).items()}
+    srv = Server(budget_bytes=int(budget_gib * (1 << 30)), capacity=256, prec="fp32", round_steps=round_steps,
+                 tiles=tiles)
     st = srv.run(trace)
     return {"workload": "Poisson arrivals, 50% 2-D 64^2-512^2 / 50% 3-D 64^3-192^3 periodic boxes with one "
                         "p=100 sphere, 50-500 steps, FP32", "requests": st["requests"], "rate_per_s": rate,
             "load_vs_capacity": load, "budget_GiB": budget_gib, "round_steps": round_steps,
             "latency_p50_s": st["latency_p50_s"], "latency_p99_s": st["latency_p99_s"],
             "zone_updates_per_s": st["zone_updates_per_s"], "rounds": st["rounds"],
-            "data_wait_mean_s": st["data_wait_mean_s"]}
+            "data_wait_mean_s": st["data_wait_mean_s"], "tiles": {str(a): v for a, v in tiles.items()}}
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def cpu_baseline(prob, min_seconds=10.0, max_steps=30):
@@ -214,6 +231,7 @@ def main():
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched and served runs")
     ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--no-tune", action="store_true", help="use the default tile shape instead of the autotuner's")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one plain 256 MiB streaming kernel (torch.mul out-of-place: reads 256 MiB, "
                          "writes 256 MiB), the reference kernel for scaling the HBM byte counters")
@@ -242,8 +260,16 @@ def main():
     for prec in ("fp32", "fp64"):
         if args.only and prec != args.only:
             continue
-        print(f"[bench] {prec} {args.n}^3 steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
-        res[prec] = run_precision(prob, prec, args.steps, args.warmup)
+        tile, tuned = 0, None
+        if not args.no_tune:
+            from paper_1607_01105_amd import autotune
+
+            tuned = autotune.tune_grid(prob, prec, steps=5, warmup=1, log=_log)
+            tile = tuned["tile"]
+        print(f"[bench] {prec} {args.n}^3 steps={args.steps} warmup={args.warmup} tile={tile}", file=sys.stderr,
+              flush=True)
+        res[prec] = run_precision(prob, prec, args.steps, args.warmup, tile)
+        res[prec]["tuned"] = tuned
         r = res[prec]
         print(f"[bench] {prec}: {r['ms'] / args.steps:.3f} ms/step, euler {r['ms_euler']:.3f} ms, "
               f"lagr {r['ms_lagr']:.3f} ms, {cells * args.steps / (r['ms'] * 1e-3):.3e} zu/s",
@@ -262,7 +288,11 @@ def main():
     achieved_tflops = flops_launch / (ms_k * 1e-3) / 1e12
     bytes_launch = algorithmic_bytes_per_zone(kern, 3, width) * cells
     achieved_gbs = bytes_launch / (ms_k * 1e-3) / 1e9
-    key = f"k_{kern}<{'float' if width == 4 else 'double'},3,32,8" + (f",{6 if width == 4 else 3}>" if kern == "lagr" else ">")
+    from paper_1607_01105_amd.ppml import ppml_tile_shape
+
+    tx, ty = ppml_tile_shape(3, r["tuned"]["tile"] if r["tuned"] else 0)
+    key = f"k_{kern}<{'float' if width == 4 else 'double'},3,{tx},{ty}" + (
+        f",{6 if width == 4 else 3}>" if kern == "lagr" else ">")
     traffic = measured_traffic(key)
     out = {
         "metric": "zone-updates/sec FP32 vs FP64 at stated L1 error; p50/p99 latency when served",
@@ -278,7 +308,10 @@ def main():
         "dtype": "f32" if head == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "grid": [args.n] * 3, "gamma": 5.0 / 3.0, "cfl": 0.3, "seed": 0,
-                   "state": head},
+                   "state": head, "tile": [tx, ty]},
+        "autotune": {p: {"ms_per_step_by_tile": {"x".join(map(str, ppml_tile_shape(3, v))): t
+                                                  for v, t in res[p]["tuned"]["ms_per_step"].items()}}
+                     for p in res if res[p]["tuned"]},
         "kernels_ms": {"euler": r["ms_euler"], "lagr": r["ms_lagr"]},
         "roofline": {"bound": "alu", "kernel": "k_" + kern, "achieved": achieved_tflops,
                      "peak": VALU_PEAK_TFLOPS[dt], "unit": "TFLOP/s", "frac": achieved_tflops / VALU_PEAK_TFLOPS[dt],
@@ -294,7 +327,8 @@ def main():
 
         r64 = res["fp64"]
         out["fp64"] = {"value": cells * args.steps / (r64["ms"] * 1e-3), "ms_per_step": r64["ms"] / args.steps,
-                       "kernels_ms": {"euler": r64["ms_euler"], "lagr": r64["ms_lagr"]}}
+                       "kernels_ms": {"euler": r64["ms_euler"], "lagr": r64["ms_lagr"]},
+                       "tile": list(ppml_tile_shape(3, r64["tuned"]["tile"] if r64["tuned"] else 0))}
         out["l1_rho_fp32_vs_fp64"] = float(np.sum(np.abs(res["fp32"]["rho"] - r64["rho"])) / np.sum(np.abs(r64["rho"])))
     if not args.no_batch and "fp32" in res:
         print("[bench] batched configuration", file=sys.stderr, flush=True)

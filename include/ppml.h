@@ -86,7 +86,20 @@ typedef struct {
     int32_t potential;     /* ppml_potential                                        */
     int32_t flags;         /* PPML_FLAG_* bits; 0 = the paper's PPML scheme          */
     double pot[8];         /* potential parameters (see ppml_potential)             */
+    int32_t tile;          /* work-group tile shape of the stage kernels: index in
+                              the list of ppml_tile_shape (0 = default); changes
+                              the speed only, never the results                  */
+    int32_t reserved;      /* must be 0                                             */
 } ppml_desc;
+
+/* Work-group tile shapes of the stage kernels for grids of ndim dimensions:
+ * ppml_tile_count returns how many there are (>= 1) or PPML_EINVAL;
+ * ppml_tile_shape gives the x and y extent of shape `variant` (a work group
+ * of tx*ty threads owns a tx x ty column of cells; 3-D kernels march it
+ * along z).  Used by the autotuner, which times the shapes on the caller's
+ * workload; every shape computes bit-identical results. */
+int ppml_tile_count(int32_t ndim);
+int ppml_tile_shape(int32_t ndim, int32_t variant, int32_t *tx, int32_t *ty);
 
 typedef struct ppml_grid ppml_grid;
 
@@ -209,6 +222,12 @@ int ppml_batch_sync(ppml_batch *b);
 
 /* Number of admitted grids and their summed state + scratch bytes. */
 int ppml_batch_info(ppml_batch *b, int32_t *count, size_t *bytes_in_use);
+
+/* Tile shape (ppml_tile_shape index) of the batch's launches for grids of
+ * ndim dimensions (default 0).  Allowed only while no grid of that
+ * dimensionality is admitted; results do not depend on it.
+ * Errors: PPML_EINVAL (ndim or variant), PPML_ESTATE. */
+int ppml_batch_set_tile(ppml_batch *b, int32_t ndim, int32_t variant);
 
 /* Destroy the batch (admitted grids become free-standing again). */
 int ppml_batch_destroy(ppml_batch *b);

@@ -35,10 +35,35 @@ int fail(int code, const char *fmt, ...)
         if (e_ != hipSuccess) return fail(PPML_EHIP, "%s: %s", #expr, hipGetErrorString(e_));          \
     } while (0)
 
-// Tile shapes per dimensionality (x extent, y extent, z chunk).
-constexpr int T1X = 256;
-constexpr int T2X = 32, T2Y = 8;
-constexpr int T3X = 32, T3Y = 8;
+// Work-group tile shapes (x extent, y extent) per dimensionality; index 0 is
+// the default.  Every shape runs the same per-cell arithmetic, so results do
+// not depend on the choice; the autotuner picks one per workload.
+template <int X, int Y> struct Tile {
+    static constexpr int tx = X, ty = Y, nt = X * Y;
+};
+constexpr int NTILE[4] = {0, 3, 4, 4};
+constexpr int TILE_X[4][4] = {{0, 0, 0, 0}, {256, 128, 64, 0}, {32, 64, 16, 32}, {32, 64, 16, 32}};
+constexpr int TILE_Y[4][4] = {{0, 0, 0, 0}, {1, 1, 1, 0}, {8, 4, 16, 4}, {8, 4, 16, 4}};
+
+// Calls f(Tile<tx, ty>{}) for tile shape v of dimensionality NDIM (the
+// tables above, spelled out as template arguments).
+template <int NDIM, typename F> void with_tile(int v, F &&f)
+{
+    if constexpr (NDIM == 1) {
+        switch (v) {
+        case 1: f(Tile<128, 1>{}); break;
+        case 2: f(Tile<64, 1>{}); break;
+        default: f(Tile<256, 1>{}); break;
+        }
+    } else {
+        switch (v) {
+        case 1: f(Tile<64, 4>{}); break;
+        case 2: f(Tile<16, 16>{}); break;
+        case 3: f(Tile<32, 4>{}); break;
+        default: f(Tile<32, 8>{}); break;
+        }
+    }
+}
 
 // Fields per LDS pass of the Lagrangian kernel (all six in FP32; FP64 in
 // two passes to keep two work groups per CU).
@@ -84,6 +109,9 @@ int validate(const ppml_desc *d)
         return fail(PPML_EINVAL, "bad potential code");
     if (d->potential == PPML_POT_LOG && !(d->pot[2] > 0.0)) return fail(PPML_EINVAL, "log potential needs q > 0");
     if (d->flags & ~PPML_FLAG_FIRST_ORDER) return fail(PPML_EINVAL, "unknown flags 0x%x", d->flags);
+    if (d->tile < 0 || d->tile >= NTILE[d->ndim])
+        return fail(PPML_EINVAL, "tile %d out of range [0, %d) for ndim %d", d->tile, NTILE[d->ndim], d->ndim);
+    if (d->reserved != 0) return fail(PPML_EINVAL, "reserved descriptor field must be 0");
     return PPML_OK;
 }
 
@@ -144,29 +172,33 @@ template <typename T> void launch_speeds(ppml_grid *g)
     }
 }
 
-template <typename T> void launch_step(ppml_grid *g, hipEvent_t *ev)
+template <typename T, int NDIM> void launch_stages(ppml_grid *g, hipEvent_t *ev)
 {
-    // ev (may be NULL): events recorded before, between and after the kernels
     const T *U = (const T *)g->state;
     T *Us = (T *)g->state;
     T *W = (T *)g->half;
-    const GridParams &gp = g->gpE;
-    int nb = gp.tiles[0] * gp.tiles[1] * gp.tiles[2];
-    if (ev) (void)hipEventRecord(ev[0], g->stream);
+    with_tile<NDIM>(g->d.tile, [&](auto tl) {
+        using TL = decltype(tl);
+        const GridParams &ge = g->gpE;
+        const GridParams &gl = g->gpL;
+        const int nbe = ge.tiles[0] * ge.tiles[1] * ge.tiles[2];
+        const int nbl = gl.tiles[0] * gl.tiles[1] * gl.tiles[2];
+        if (ev) (void)hipEventRecord(ev[0], g->stream);
+        k_euler<T, NDIM, TL::tx, TL::ty><<<nbe, TL::nt, 0, g->stream>>>(U, W, ge, g->ctrl);
+        if (ev) (void)hipEventRecord(ev[1], g->stream);
+        k_lagr<T, NDIM, TL::tx, TL::ty, LG<T>::g><<<nbl, TL::nt, 0, g->stream>>>(W, Us, gl, g->ctrl);
+        if (ev) (void)hipEventRecord(ev[2], g->stream);
+    });
+}
+
+template <typename T> void launch_step(ppml_grid *g, hipEvent_t *ev)
+{
+    // ev (may be NULL): events recorded before, between and after the kernels
     switch (g->d.ndim) {
-    case 1: k_euler<T, 1, T1X, 1><<<nb, T1X, 0, g->stream>>>(U, W, gp, g->ctrl); break;
-    case 2: k_euler<T, 2, T2X, T2Y><<<nb, T2X * T2Y, 0, g->stream>>>(U, W, gp, g->ctrl); break;
-    default: k_euler<T, 3, T3X, T3Y><<<nb, T3X * T3Y, 0, g->stream>>>(U, W, gp, g->ctrl); break;
+    case 1: launch_stages<T, 1>(g, ev); break;
+    case 2: launch_stages<T, 2>(g, ev); break;
+    default: launch_stages<T, 3>(g, ev); break;
     }
-    if (ev) (void)hipEventRecord(ev[1], g->stream);
-    const GridParams &gl = g->gpL;
-    nb = gl.tiles[0] * gl.tiles[1] * gl.tiles[2];
-    switch (g->d.ndim) {
-    case 1: k_lagr<T, 1, T1X, 1, LG<T>::g><<<nb, T1X, 0, g->stream>>>(W, Us, gl, g->ctrl); break;
-    case 2: k_lagr<T, 2, T2X, T2Y, LG<T>::g><<<nb, T2X * T2Y, 0, g->stream>>>(W, Us, gl, g->ctrl); break;
-    default: k_lagr<T, 3, T3X, T3Y, LG<T>::g><<<nb, T3X * T3Y, 0, g->stream>>>(W, Us, gl, g->ctrl); break;
-    }
-    if (ev) (void)hipEventRecord(ev[2], g->stream);
 }
 
 template <typename T> void launch_totals(ppml_grid *g, double mean_cells)
@@ -253,18 +285,41 @@ int choose_chunks(long long tiles_xy, int nz, long long slots, double warm)
     return best;
 }
 
-template <typename T> void stage_slots(int device, long long &slots_e, long long &slots_l)
+template <typename T> void stage_slots(int device, int tile, long long &slots_e, long long &slots_l)
 {
     int cus = 0, be = 0, bl = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&be, k_euler<T, 3, T3X, T3Y>, T3X * T3Y, 0) != hipSuccess) be = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bl, k_lagr<T, 3, T3X, T3Y, LG<T>::g>, T3X * T3Y, 0) !=
-        hipSuccess)
-        bl = 0;
+    with_tile<3>(tile, [&](auto tl) {
+        using TL = decltype(tl);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&be, k_euler<T, 3, TL::tx, TL::ty>, TL::nt, 0) != hipSuccess)
+            be = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bl, k_lagr<T, 3, TL::tx, TL::ty, LG<T>::g>, TL::nt, 0) !=
+            hipSuccess)
+            bl = 0;
+    });
     (void)hipGetLastError();
     if (cus < 1) cus = 256;
     slots_e = (long long)cus * (be > 0 ? be : 2);
     slots_l = (long long)cus * (bl > 0 ? bl : 2);
+}
+
+// Work-group tiling of a grid for tile shape v: x/y tiles, and the z chunk
+// of the batched launches (small enough that a 3-D grid alone gives the
+// launch a few thousand work groups).
+void set_tiling(GridParams &gp, int ndim, int v)
+{
+    const int tx = TILE_X[ndim][v], ty = TILE_Y[ndim][v];
+    gp.tiles[0] = (gp.n[0] + tx - 1) / tx;
+    gp.tiles[1] = ndim >= 2 ? (gp.n[1] + ty - 1) / ty : 1;
+    gp.tiles[2] = 1;
+    gp.cz = 1;
+    if (ndim == 3) {
+        long long tiles = (long long)gp.tiles[0] * gp.tiles[1];
+        int cz = gp.n[2];
+        while (cz > 16 && tiles * ((gp.n[2] + cz - 1) / cz) < 2048) cz = (cz + 1) / 2;
+        gp.cz = cz;
+        gp.tiles[2] = (gp.n[2] + cz - 1) / cz;
+    }
 }
 
 void set_chunks(GridParams &gp, int chunks)
@@ -330,26 +385,7 @@ int ppml_create(const ppml_desc *d, void *state_dev, void *scratch_dev, void *hi
     gp.potential = d->potential;
     gp.first_order = (d->flags & PPML_FLAG_FIRST_ORDER) ? 1 : 0;
     for (int i = 0; i < 8; i++) gp.pot[i] = d->pot[i];
-    // tiles of the stage kernels; 3-D: z chunk small enough that the launch
-    // has enough work groups to fill 256 CUs several times over
-    if (d->ndim == 1) {
-        gp.tiles[0] = (gp.n[0] + T1X - 1) / T1X;
-        gp.tiles[1] = gp.tiles[2] = 1;
-        gp.cz = 1;
-    } else if (d->ndim == 2) {
-        gp.tiles[0] = (gp.n[0] + T2X - 1) / T2X;
-        gp.tiles[1] = (gp.n[1] + T2Y - 1) / T2Y;
-        gp.tiles[2] = 1;
-        gp.cz = 1;
-    } else {
-        gp.tiles[0] = (gp.n[0] + T3X - 1) / T3X;
-        gp.tiles[1] = (gp.n[1] + T3Y - 1) / T3Y;
-        long long tiles = (long long)gp.tiles[0] * gp.tiles[1];
-        int cz = gp.n[2];
-        while (cz > 16 && tiles * ((gp.n[2] + cz - 1) / cz) < 2048) cz = (cz + 1) / 2;
-        gp.cz = cz;
-        gp.tiles[2] = (gp.n[2] + cz - 1) / cz;
-    }
+    set_tiling(gp, d->ndim, d->tile);
     g->gpE = gp;
     g->gpL = gp;
     if (d->ndim == 3) {
@@ -357,8 +393,8 @@ int ppml_create(const ppml_desc *d, void *state_dev, void *scratch_dev, void *hi
         // stage kernel (start-up cost: 3 z-only planes in the Eulerian
         // kernel, 6 in the Lagrangian kernel)
         long long se, sl;
-        if (d->prec == PPML_FP64) stage_slots<double>(g->device, se, sl);
-        else stage_slots<float>(g->device, se, sl);
+        if (d->prec == PPML_FP64) stage_slots<double>(g->device, d->tile, se, sl);
+        else stage_slots<float>(g->device, d->tile, se, sl);
         const long long txy = (long long)gp.tiles[0] * gp.tiles[1];
         set_chunks(g->gpE, choose_chunks(txy, gp.n[2], se, 1.5));
         set_chunks(g->gpL, choose_chunks(txy, gp.n[2], sl, 3.0));
@@ -628,6 +664,21 @@ const char *ppml_last_error(void) { return g_err; }
 
 int ppml_version(void) { return 100; }
 
+int ppml_tile_count(int32_t ndim)
+{
+    if (ndim < 1 || ndim > 3) return fail(PPML_EINVAL, "ndim must be 1, 2 or 3 (got %d)", ndim);
+    return NTILE[ndim];
+}
+
+int ppml_tile_shape(int32_t ndim, int32_t variant, int32_t *tx, int32_t *ty)
+{
+    if (ndim < 1 || ndim > 3) return fail(PPML_EINVAL, "ndim must be 1, 2 or 3 (got %d)", ndim);
+    if (variant < 0 || variant >= NTILE[ndim]) return fail(PPML_EINVAL, "tile %d out of range", variant);
+    if (tx) *tx = TILE_X[ndim][variant];
+    if (ty) *ty = TILE_Y[ndim][variant];
+    return PPML_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
@@ -647,6 +698,7 @@ struct ppml_batch {
     int *h_steps;
     std::vector<int> entry_slot;
     int goff[4], gn[4], gtiles[4];
+    int tile[4];          // tile shape of the launches per dimensionality
     bool dirty;
     long long version;
     hipGraph_t graph;
@@ -671,12 +723,13 @@ int batch_rebuild(ppml_batch *b)
             if (!g || g->d.ndim != nd) continue;
             BatchEntry &e = b->h_ents[n];
             e.gp = g->gp;
+            set_tiling(e.gp, nd, b->tile[nd]);
             e.state = g->state;
             e.half = g->half;
             e.ctrl = g->ctrl;
             e.tile0 = tiles;
             e.pad = 0;
-            tiles += g->gp.tiles[0] * g->gp.tiles[1] * g->gp.tiles[2];
+            tiles += e.gp.tiles[0] * e.gp.tiles[1] * e.gp.tiles[2];
             b->entry_slot.push_back(s);
             n++;
         }
@@ -692,22 +745,28 @@ int batch_rebuild(ppml_batch *b)
     return PPML_OK;
 }
 
+template <typename T, int NDIM> void batch_stage(ppml_batch *b, bool lagr)
+{
+    if (!b->gn[NDIM]) return;
+    with_tile<NDIM>(b->tile[NDIM], [&](auto tl) {
+        using TL = decltype(tl);
+        const BatchEntry *e = b->d_ents + b->goff[NDIM];
+        if (lagr)
+            k_lagr_batch<T, NDIM, TL::tx, TL::ty, LG<T>::g><<<b->gtiles[NDIM], TL::nt, 0, b->stream>>>(e, b->gn[NDIM]);
+        else
+            k_euler_batch<T, NDIM, TL::tx, TL::ty><<<b->gtiles[NDIM], TL::nt, 0, b->stream>>>(e, b->gn[NDIM]);
+    });
+}
+
 template <typename T> void batch_enqueue(ppml_batch *b, int nsteps)
 {
     for (int s = 0; s < nsteps; s++) {
-        if (b->gn[1]) k_euler_batch<T, 1, T1X, 1><<<b->gtiles[1], T1X, 0, b->stream>>>(b->d_ents + b->goff[1], b->gn[1]);
-        if (b->gn[2])
-            k_euler_batch<T, 2, T2X, T2Y><<<b->gtiles[2], T2X * T2Y, 0, b->stream>>>(b->d_ents + b->goff[2], b->gn[2]);
-        if (b->gn[3])
-            k_euler_batch<T, 3, T3X, T3Y><<<b->gtiles[3], T3X * T3Y, 0, b->stream>>>(b->d_ents + b->goff[3], b->gn[3]);
-        if (b->gn[1])
-            k_lagr_batch<T, 1, T1X, 1, LG<T>::g><<<b->gtiles[1], T1X, 0, b->stream>>>(b->d_ents + b->goff[1], b->gn[1]);
-        if (b->gn[2])
-            k_lagr_batch<T, 2, T2X, T2Y, LG<T>::g>
-                <<<b->gtiles[2], T2X * T2Y, 0, b->stream>>>(b->d_ents + b->goff[2], b->gn[2]);
-        if (b->gn[3])
-            k_lagr_batch<T, 3, T3X, T3Y, LG<T>::g>
-                <<<b->gtiles[3], T3X * T3Y, 0, b->stream>>>(b->d_ents + b->goff[3], b->gn[3]);
+        batch_stage<T, 1>(b, false);
+        batch_stage<T, 2>(b, false);
+        batch_stage<T, 3>(b, false);
+        batch_stage<T, 1>(b, true);
+        batch_stage<T, 2>(b, true);
+        batch_stage<T, 3>(b, true);
     }
 }
 
@@ -742,6 +801,7 @@ int ppml_batch_create(int32_t capacity, size_t budget_bytes, void *hip_stream, p
     b->h_ents = nullptr;
     b->h_steps = nullptr;
     b->dirty = true;
+    for (int nd = 0; nd < 4; nd++) b->tile[nd] = 0;
     b->version = 0;
     b->graph = nullptr;
     b->exec = nullptr;
@@ -874,6 +934,18 @@ int ppml_batch_info(ppml_batch *b, int32_t *count, size_t *bytes_in_use)
     for (ppml_grid *x : b->slots) n += x ? 1 : 0;
     if (count) *count = n;
     if (bytes_in_use) *bytes_in_use = b->in_use;
+    return PPML_OK;
+}
+
+int ppml_batch_set_tile(ppml_batch *b, int32_t ndim, int32_t variant)
+{
+    if (!b) return fail(PPML_EINVAL, "batch is NULL");
+    if (ndim < 1 || ndim > 3) return fail(PPML_EINVAL, "ndim must be 1, 2 or 3 (got %d)", ndim);
+    if (variant < 0 || variant >= NTILE[ndim]) return fail(PPML_EINVAL, "tile %d out of range", variant);
+    for (ppml_grid *x : b->slots)
+        if (x && x->d.ndim == ndim) return fail(PPML_ESTATE, "grids of ndim %d are admitted", ndim);
+    b->tile[ndim] = variant;
+    b->dirty = true;
     return PPML_OK;
 }
 

@@ -782,6 +782,9 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
 #pragma unroll
         for (int pass = 0; pass < NPASS; pass++) {
             const int f0 = pass * G;
+            // the previous pass reads its tile (own cell values) after its last
+            // barrier: every wave must be done before the tile is overwritten
+            if (pass > 0) __syncthreads();
             if constexpr (PIPE) {
                 // the cross tile of plane k was sent to LDS one plane ago:
                 // wait for this wave's transfers, then mirror the normal

@@ -34,6 +34,7 @@ class ppml_desc(C.Structure):
         ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("gamma", C.c_double), ("cfl", C.c_double),
         ("bc_lo", C.c_int32 * 3), ("bc_hi", C.c_int32 * 3), ("vacuum_ratio", C.c_double),
         ("potential", C.c_int32), ("flags", C.c_int32), ("pot", C.c_double * 8),
+        ("tile", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -49,7 +50,7 @@ EXPORTS = (
     "ppml_step", "ppml_get_time", "ppml_max_speeds", "ppml_get_conserved", "ppml_totals", "ppml_sync",
     "ppml_destroy", "ppml_strerror", "ppml_last_error", "ppml_version", "ppml_set_timing", "ppml_get_timing",
     "ppml_batch_create", "ppml_batch_admit", "ppml_batch_retire", "ppml_batch_step", "ppml_batch_sync",
-    "ppml_batch_info", "ppml_batch_destroy",
+    "ppml_batch_info", "ppml_batch_destroy", "ppml_tile_count", "ppml_tile_shape", "ppml_batch_set_tile",
 )
 
 _libs: dict[str, C.CDLL] = {}
@@ -91,6 +92,9 @@ def load(path: str | None = None) -> C.CDLL:
     lib.ppml_batch_sync.argtypes = [vp]
     lib.ppml_batch_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_size_t)]
     lib.ppml_batch_destroy.argtypes = [vp]
+    lib.ppml_tile_count.argtypes = [C.c_int32]
+    lib.ppml_tile_shape.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    lib.ppml_batch_set_tile.argtypes = [vp, C.c_int32, C.c_int32]
     lib.ppml_strerror.restype = C.c_char_p
     lib.ppml_strerror.argtypes = [C.c_int]
     lib.ppml_last_error.restype = C.c_char_p
@@ -110,7 +114,7 @@ def _check(lib, rc):
 
 
 def make_desc(ndim, n, lo, hi, gamma, cfl, bc="periodic", prec="fp64", vacuum_ratio=1e-5, potential=None,
-              first_order=False):
+              first_order=False, tile=0):
     d = ppml_desc()
     d.ndim = int(ndim)
     d.prec = PREC[prec] if isinstance(prec, str) else int(prec)
@@ -133,6 +137,8 @@ def make_desc(ndim, n, lo, hi, gamma, cfl, bc="periodic", prec="fp64", vacuum_ra
     d.vacuum_ratio = float(vacuum_ratio)
     d.potential = POT[potential[0]] if potential else PPML_POT_NONE
     d.flags = PPML_FLAG_FIRST_ORDER if first_order else 0
+    d.tile = int(tile)
+    d.reserved = 0
     if potential:
         for i, v in enumerate(potential[1:]):
             d.pot[i] = float(v)
@@ -156,6 +162,21 @@ def ppml_create(desc, state_ptr: int, scratch_ptr: int, stream: int, lib=None):
     return h
 
 
+def ppml_tile_count(ndim, lib=None) -> int:
+    lib = lib or load()
+    rc = lib.ppml_tile_count(int(ndim))
+    if rc < 0:
+        _check(lib, rc)
+    return int(rc)
+
+
+def ppml_tile_shape(ndim, variant, lib=None) -> tuple[int, int]:
+    lib = lib or load()
+    tx, ty = C.c_int32(), C.c_int32()
+    _check(lib, lib.ppml_tile_shape(int(ndim), int(variant), C.byref(tx), C.byref(ty)))
+    return tx.value, ty.value
+
+
 def _dp(a):
     return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
 
@@ -173,11 +194,11 @@ class Grid:
     """One grid on the current GPU; state and scratch are torch tensors."""
 
     def __init__(self, ndim, n, lo, hi, gamma, cfl, bc="periodic", prec="fp64", vacuum_ratio=1e-5,
-                 potential=None, device="cuda", stream=None, exact=False, first_order=False, lib_path=None):
+                 potential=None, device="cuda", stream=None, exact=False, first_order=False, lib_path=None, tile=0):
         import torch
 
         self.lib = load(lib_path or (LIB_EXACT_PATH if exact else LIB_PATH))
-        self.desc = make_desc(ndim, n, lo, hi, gamma, cfl, bc, prec, vacuum_ratio, potential, first_order)
+        self.desc = make_desc(ndim, n, lo, hi, gamma, cfl, bc, prec, vacuum_ratio, potential, first_order, tile)
         self.ndim = int(ndim)
         self.ncell = int(self.desc.n[0] * self.desc.n[1] * self.desc.n[2])
         sb = ppml_state_bytes(self.desc, self.lib)
@@ -331,4 +352,9 @@ class Batch:
         b = C.c_size_t()
         _check(self.lib, self.lib.ppml_batch_info(self.h, C.byref(n), C.byref(b)))
         return n.value, b.value
+
+    def set_tile(self, ndim, variant):
+        """Tile shape of the launches for grids of ndim dimensions (before any
+        such grid is admitted)."""
+        _check(self.lib, self.lib.ppml_batch_set_tile(self.h, int(ndim), int(variant)))
 

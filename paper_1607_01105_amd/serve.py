@@ -53,7 +53,7 @@ class Server:
 
     def __init__(self, budget_bytes: int = 4 << 30, capacity: int = 256, prec: str = "fp32", round_steps: int = 50,
                  graph: bool = False, device: str = "cuda", prep_workers: int = 8, lookahead: int = 16,
-                 keep_results: bool = False, batch=None):
+                 keep_results: bool = False, batch=None, tiles: dict | None = None):
         from .ppml import Batch
 
         self.prec = prec
@@ -61,6 +61,8 @@ class Server:
         self.graph = graph
         self.budget = int(budget_bytes)
         self.batch = batch if batch is not None else Batch(capacity, budget_bytes, device)
+        for nd, v in (tiles or {}).items():  # tile shape per dimensionality (autotune.tune_batch)
+            self.batch.set_tile(nd, v)
         self.capacity = capacity
         self.prep_workers = prep_workers
         self.lookahead = lookahead

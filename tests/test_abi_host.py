@@ -77,7 +77,7 @@ def test_state_and_scratch_bytes(lib):
 
 @pytest.mark.parametrize("bad", [dict(ndim=4), dict(gamma=1.0), dict(cfl=1.0), dict(cfl=0.0),
                                  dict(n=(0, 8, 4)), dict(hi=(0, 1, 1)), dict(bc="reflect", n=(2, 8, 4)),
-                                 dict(vacuum_ratio=-1.0)])
+                                 dict(vacuum_ratio=-1.0), dict(tile=-1), dict(tile=99)])
 def test_invalid_descriptors_rejected(lib, bad):
     from paper_1607_01105_amd import ppml
 
@@ -103,3 +103,43 @@ def test_null_grid_rejected(lib):
 
     assert lib.ppml_step(None, 1, 0.0, 0.0) == ppml.PPML_EINVAL
     assert lib.ppml_destroy(None) == ppml.PPML_EINVAL
+
+
+def test_reserved_descriptor_field_must_be_zero(lib):
+    from paper_1607_01105_amd import ppml
+
+    d = _desc()
+    d.reserved = 1
+    assert ppml.ppml_state_bytes(d, lib) == 0
+
+
+def test_tile_shape_queries(lib):
+    """Every dimensionality offers at least the default shape; shapes are
+    whole waves of at most 1024 threads, 1-D shapes have ty = 1, and every
+    listed shape is accepted in a descriptor."""
+    from paper_1607_01105_amd import ppml
+
+    for nd in (1, 2, 3):
+        cnt = ppml.ppml_tile_count(nd, lib)
+        assert cnt >= 1
+        shapes = [ppml.ppml_tile_shape(nd, v, lib) for v in range(cnt)]
+        assert len(set(shapes)) == cnt
+        for tx, ty in shapes:
+            assert tx * ty % 64 == 0 and tx * ty <= 1024
+            assert nd >= 2 or ty == 1
+        for v in range(cnt):
+            n = {1: (100,), 2: (40, 30), 3: (20, 12, 8)}[nd]
+            d = ppml.make_desc(nd, n, (0,) * nd, (1,) * nd, 1.4, 0.3, tile=v)
+            assert ppml.ppml_state_bytes(d, lib) > 0
+    for nd in (0, 4):
+        assert lib.ppml_tile_count(nd) == ppml.PPML_EINVAL
+    with pytest.raises(ppml.PPMLError):
+        ppml.ppml_tile_shape(3, ppml.ppml_tile_count(3, lib), lib)
+
+
+def test_autotune_pick_prefers_fastest_then_default():
+    from paper_1607_01105_amd.autotune import pick
+
+    assert pick({0: 1.0, 1: 0.5, 2: 0.7}) == 1
+    assert pick({0: 0.5, 1: 0.5}) == 0
+    assert pick({2: 0.3, 1: 0.3, 3: 0.9}) == 1
