@@ -195,6 +195,76 @@ def run_served(n_requests=60, load=0.5, seed=0, budget_gib=4.0, round_steps=50, 
             "data_wait_mean_s": st["data_wait_mean_s"], "tiles": {str(a): v for a, v in tiles.items()}}
 
 
+def run_disk(steps=500):
+    """Rotating-disk configuration: 512 x 512 x 64, logarithmic potential,
+    outflow, CFL 0.2, 500 steps.  FP32 (the configuration's state) and FP64,
+    each with its own CFL steps, with the L1 distance of the two densities."""
+    import numpy as np
+    import torch
+
+    from paper_1607_01105_amd import workloads as W
+    from paper_1607_01105_amd.ppml import Grid
+
+    prob = W.disk(nsteps=steps)
+    out = {"workload": "rotating gas disk 512x512x64 in a logarithmic potential, outflow, CFL 0.2, "
+                       f"{steps} steps", "cells": prob.cells, "steps": steps}
+    for prec in ("fp32", "fp64"):
+        g = Grid.from_problem(prob, prec=prec)
+        g.sync()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(g.stream)
+        g.step(steps)
+        t1.record(g.stream)
+        g.sync()
+        ms = t0.elapsed_time(t1)
+        t, _, n = g.time()
+        out[prec] = {"zone_updates_per_s": prob.cells * steps / (ms * 1e-3), "ms_per_step": ms / steps, "t": t}
+        del g
+        torch.cuda.empty_cache()
+    # accuracy at equal times (untimed): FP64 with its CFL steps, one at a
+    # time to record them, and FP32 driven by the same steps
+    g64 = Grid.from_problem(prob, prec="fp64")
+    taus = []
+    for _ in range(steps):
+        g64.step(1)
+        taus.append(g64.time()[1])
+    rho64 = g64.get("rho")
+    del g64
+    g32 = Grid.from_problem(prob, prec="fp32")
+    for tau in taus:
+        g32.step(1, dt_fixed=float(tau))
+    rho32 = g32.get("rho")
+    del g32
+    torch.cuda.empty_cache()
+    out["l1_rho_fp32_vs_fp64_same_steps"] = float(np.sum(np.abs(rho32 - rho64)) / np.sum(np.abs(rho64)))
+    return out
+
+
+def run_riemann_1d(seeds=range(16)):
+    """1-D Riemann configuration: 512 cells, FP64, 16 seeds, each run to
+    t = 0.15 with its own CFL steps (latency-bound: two small launches per
+    step)."""
+    import torch
+
+    from paper_1607_01105_amd import workloads as W
+    from paper_1607_01105_amd.ppml import Grid
+
+    zu, sec = 0, 0.0
+    for s in seeds:
+        prob = W.riemann_1d(s)
+        g = Grid.from_problem(prob, prec="fp64")
+        g.sync()
+        t0 = time.perf_counter()
+        _, _, n = g.run_to(prob.t_stop)
+        sec += time.perf_counter() - t0
+        zu += prob.cells * n
+        del g
+    torch.cuda.empty_cache()
+    return {"workload": "1-D Riemann, 512 cells, FP64, seeds 0-15, t = 0.15 (host-driven chunks of 64 steps)",
+            "zone_updates_per_s": zu / sec, "zone_updates": zu, "seconds": sec}
+
+
 def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -215,10 +285,21 @@ def cpu_baseline(prob, min_seconds=10.0, max_steps=30):
         sec += time.perf_counter() - t0
         steps += 1
     cores = oracle.max_threads()
+    # the same stepping on one core (results are independent of the threads)
+    oracle.set_threads(1)
+    steps1, sec1 = 0, 0.0
+    while steps1 < 1 or (sec1 < 5.0 and steps1 < max_steps):
+        tau = o.dt()
+        t0 = time.perf_counter()
+        o.step(tau)
+        sec1 += time.perf_counter() - t0
+        steps1 += 1
+    oracle.set_threads(cores)
     del o
     return {"value": prob.cells * steps / sec, "unit": "zone-updates/s", "cores": cores, "kind": "oracle",
             "sample": f"first {steps} steps of the same 256^3 workload ({prob.cells * steps} zone-updates), "
-                      f"FP64, {sec:.1f} s of stepping"}
+                      f"FP64, {sec:.1f} s of stepping on {cores} threads; then {steps1} more step(s) on 1 thread",
+            "one_core_value": prob.cells * steps1 / sec1}
 
 
 def main():
@@ -338,6 +419,13 @@ def main():
         out["served"] = run_served(n_requests=args.serve_requests, capacity_zu_per_s=value)
         print(f"[bench] served: p50 {out['served']['latency_p50_s']:.3f} s, p99 {out['served']['latency_p99_s']:.3f} s",
               file=sys.stderr, flush=True)
+    if not args.no_batch:
+        print("[bench] disk configuration", file=sys.stderr, flush=True)
+        out["disk"] = run_disk()
+        print(f"[bench] disk: fp32 {out['disk']['fp32']['zone_updates_per_s']:.3e} zu/s, "
+              f"fp64 {out['disk']['fp64']['zone_updates_per_s']:.3e} zu/s", file=sys.stderr, flush=True)
+        print("[bench] 1-D Riemann configuration", file=sys.stderr, flush=True)
+        out["riemann_1d"] = run_riemann_1d()
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob)

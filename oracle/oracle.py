@@ -78,6 +78,8 @@ def load_library(path: str | None = None) -> C.CDLL:
     lib.og_avg_left.argtypes = [C.c_double] * 4
     lib.og_max_threads.restype = C.c_int
     lib.og_max_threads.argtypes = []
+    lib.og_set_threads.restype = None
+    lib.og_set_threads.argtypes = [C.c_int]
     lib.og_avg_right.restype = C.c_double
     lib.og_avg_right.argtypes = [C.c_double] * 4
     _cache[path] = lib
@@ -95,6 +97,11 @@ def _f64(a) -> np.ndarray:
 def max_threads(lib: C.CDLL | None = None) -> int:
     """Threads the oracle's OpenMP loops use."""
     return int((lib or load_library()).og_max_threads())
+
+
+def set_threads(n: int, lib: C.CDLL | None = None) -> None:
+    """Threads for the oracle's OpenMP loops from now on (timing only)."""
+    (lib or load_library()).og_set_threads(int(n))
 
 
 def reconstruct_line(q, lib: C.CDLL | None = None):

@@ -713,10 +713,14 @@ long og_run(og_grid *g, long nsteps, double dt_fixed, double t_stop, double *tau
     return taken;
 }
 
-/* Threads the oracle's parallel loops use (for reporting). */
+/* Threads the oracle's parallel loops use (for reporting), and a setter for
+ * timing it on a given number of cores (results do not depend on it: the
+ * only reduction is an exact maximum). */
 #ifdef _OPENMP
 #include <omp.h>
 int og_max_threads(void) { return omp_get_max_threads(); }
+void og_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
 #else
 int og_max_threads(void) { return 1; }
+void og_set_threads(int n) { (void)n; }
 #endif

@@ -169,3 +169,67 @@ class Server:
             "data_wait_mean_s": float(np.mean([c.data_wait for c in done])),
             "completed": done,
         }
+
+
+def measure_capacity(n_requests=300, seed=1000, budget_bytes=4 << 30, round_steps=50, tiles=None, log=None) -> float:
+    """Saturated throughput of the server (zone-updates/s): every request of
+    a trace is present at time zero, so the batch is always full."""
+    from . import workloads as W
+
+    trace = W.served_trace(seed, n_requests, 1.0)
+    srv = Server(budget_bytes=budget_bytes, capacity=256, round_steps=round_steps, tiles=tiles,
+                 prep_workers=16, lookahead=64)
+    st = srv.run(trace, time_scale=0.0, log=log)
+    return st["zone_updates_per_s"]
+
+
+def main(argv=None):
+    """Served runs at several loads: python -m paper_1607_01105_amd.serve."""
+    import argparse
+    import json
+    import sys
+
+    import torch
+
+    from . import autotune
+    from . import workloads as W
+
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--loads", default="0.25,0.5,0.8", help="arrival rates as fractions of the saturated capacity")
+    ap.add_argument("--budget-gib", type=float, default=4.0)
+    ap.add_argument("--round-steps", type=int, default=50)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--capacity-requests", type=int, default=300)
+    a = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    budget = int(a.budget_gib * (1 << 30))
+    sample = [r.problem() for r in W.served_trace(a.seed + 1, 6, 1.0, n2_range=(64, 256), n3_range=(64, 96))]
+    tiles = {nd: r["tile"] for nd, r in autotune.tune_batch(sample, prec="fp32", steps=4, log=log).items()}
+    cap = measure_capacity(a.capacity_requests, seed=a.seed + 1000, budget_bytes=budget, round_steps=a.round_steps,
+                           tiles=tiles, log=log)
+    probe = W.served_trace(a.seed, 4000, 1.0)
+    mean_zu = sum(r.cells * r.steps for r in probe) / len(probe)
+    log(f"[serve] saturated capacity {cap:.3e} zone-updates/s; mean work {mean_zu:.3e} zone-updates per request")
+    for load in [float(x) for x in a.loads.split(",")]:
+        rate = load * cap / mean_zu
+        trace = W.served_trace(a.seed, a.requests, rate)
+        log(f"[serve] load {load:.2f}: {a.requests} requests at {rate:.2f}/s")
+        srv = Server(budget_bytes=budget, capacity=256, round_steps=a.round_steps, tiles=tiles, prep_workers=16,
+                     lookahead=64)
+        st = srv.run(trace, log=log)  # one line per completed request
+        out = {"load_vs_capacity": load, "rate_per_s": rate, "requests": st["requests"],
+               "capacity_zone_updates_per_s": cap, "zone_updates_per_s": st["zone_updates_per_s"],
+               "latency_p50_s": st["latency_p50_s"], "latency_p99_s": st["latency_p99_s"],
+               "latency_mean_s": st["latency_mean_s"], "data_wait_mean_s": st["data_wait_mean_s"],
+               "rounds": st["rounds"], "wall_s": st["wall_s"], "budget_GiB": a.budget_gib,
+               "round_steps": a.round_steps, "tiles": {str(k): v for k, v in tiles.items()}}
+        print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
