@@ -141,6 +141,23 @@ template <typename T> struct Parab {
 
 template <typename T> __device__ __forceinline__ Parab<T> monotonize(T c, T l, T r)
 {
+#ifndef PPML_EXACT
+    // The same rules in terms of the one-sided jumps dl = c - l, dr = r - c:
+    // with dl, dr of one sign (otherwise the cell is flattened),
+    // d * q6 > d^2 <=> (dl - 2 dr)(dl + dr) > 0 <=> |dl| > 2|dr|, where the new
+    // left edge 3c - 2r = c - 2 dr; d * q6 < -d^2 <=> |dr| > 2|dl|, new right
+    // edge c + 2 dl.  Equal to the rounding of the two forms (the limiter is
+    // continuous across every branch boundary).
+    const T dl = c - l, dr = r - c;
+    const bool flat = dl * dr <= T(0);
+    const T L = flat ? c : (dabs(dl) > K<T>::two * dabs(dr) ? c - K<T>::two * dr : l);
+    const T R = flat ? c : (dabs(dr) > K<T>::two * dabs(dl) ? c + K<T>::two * dl : r);
+    Parab<T> q;
+    q.L = L;
+    q.R = R;
+    q.Q6 = K<T>::six * (c - K<T>::half * (L + R));
+    return q;
+#endif
     if ((r - c) * (c - l) <= T(0)) {
         l = c;
         r = c;
@@ -169,6 +186,30 @@ template <typename T> __device__ __forceinline__ Parab<T> parabola5(T qm2, T qm1
     T l = interface_value(qm1, q0, dmm, dm0);
     T r = interface_value(q0, qp1, dm0, dmp);
     return monotonize(q0, l, r);
+}
+
+// Parabolas of two neighbouring cells q0, q1 of a line (values qm2 .. q3),
+// sharing the slopes and the interface value between them: each parabola is
+// computed by the same operations as parabola5 of its cell.  Constant states
+// in the first-order scheme.
+template <typename T>
+__device__ __forceinline__ void parabola_pair(int first_order, T qm2, T qm1, T q0, T q1, T q2, T q3, Parab<T> &a,
+                                              Parab<T> &b)
+{
+    if (first_order) {
+        a = Parab<T>{q0, q0, T(0)};
+        b = Parab<T>{q1, q1, T(0)};
+        return;
+    }
+    const T sm = limited_slope(qm2, qm1, q0);
+    const T s0 = limited_slope(qm1, q0, q1);
+    const T s1 = limited_slope(q0, q1, q2);
+    const T s2 = limited_slope(q1, q2, q3);
+    const T il = interface_value(qm1, q0, sm, s0);  // left edge of cell 0
+    const T ic = interface_value(q0, q1, s0, s1);   // between the cells
+    const T ir = interface_value(q1, q2, s1, s2);   // right edge of cell 1
+    a = monotonize(q0, il, ic);
+    b = monotonize(q1, ic, ir);
 }
 
 // State profile of a cell: the monotonised parabola, or the constant cell

@@ -200,6 +200,10 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
     constexpr int PS = PW * PH;
     constexpr int NXP = (TX + 2) * TY;
     constexpr int NYP = NDIM >= 2 ? TX * (TY + 2) : 1;
+    static_assert(TX % 2 == 0 && (NDIM < 2 || TY % 2 == 0), "parabola pairs need even tile extents");
+    constexpr int PXR = (TX + 2) / 2;                     // x pairs per row
+    constexpr int NXR = PXR * TY;                         // x pair jobs
+    constexpr int NYR = NDIM >= 2 ? TX * ((TY + 2) / 2) : 0;  // y pair jobs
     constexpr int NXI = (TX + 1) * TY;
     constexpr int NYI = NDIM >= 2 ? TX * (TY + 1) : 1;
 
@@ -386,18 +390,29 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
             s_ps[li] = p * s;
         }
         __syncthreads();
-        for (int j = tid; j < NXP; j += NT) {
-            const int cx = j % (TX + 2), cy = j / (TX + 2);
-            const int li = (cy + HY) * PW + cx + 2;
-            xv[j] = profile5(gp.first_order, s_vx[li - 2], s_vx[li - 1], s_vx[li], s_vx[li + 1], s_vx[li + 2]);
-            xp[j] = profile5(gp.first_order, s_p[li - 2], s_p[li - 1], s_p[li], s_p[li + 1], s_p[li + 2]);
-        }
-        if constexpr (NDIM >= 2) {
-            for (int j = tid; j < NYP; j += NT) {
-                const int cx = j % TX, cy = j / TX;
+        // parabolas of v_d and p, two neighbouring cells per job (shared slopes
+        // and interface value): x pairs of each row, then y pairs of each
+        // column, in one job space
+        for (int j = tid; j < NXR + NYR; j += NT) {
+            if (j < NXR) {
+                const int pr = j % PXR, cy = j / PXR;
+                const int cx = 2 * pr;  // first cell of the pair (tile-rel x = cx - 1)
+                const int li = (cy + HY) * PW + cx + 2;
+                const int o = cy * (TX + 2) + cx;
+                parabola_pair(gp.first_order, s_vx[li - 2], s_vx[li - 1], s_vx[li], s_vx[li + 1], s_vx[li + 2],
+                              s_vx[li + 3], xv[o], xv[o + 1]);
+                parabola_pair(gp.first_order, s_p[li - 2], s_p[li - 1], s_p[li], s_p[li + 1], s_p[li + 2],
+                              s_p[li + 3], xp[o], xp[o + 1]);
+            } else if constexpr (NDIM >= 2) {
+                const int jj = j - NXR;
+                const int cx = jj % TX, pr = jj / TX;
+                const int cy = 2 * pr;  // first cell of the pair (tile-rel y = cy - 1)
                 const int li = (cy - 1 + HY) * PW + cx + HX;
-                yv[j] = profile5(gp.first_order, s_vy[li - 2 * PW], s_vy[li - PW], s_vy[li], s_vy[li + PW], s_vy[li + 2 * PW]);
-                yp[j] = profile5(gp.first_order, s_p[li - 2 * PW], s_p[li - PW], s_p[li], s_p[li + PW], s_p[li + 2 * PW]);
+                const int o = cy * TX + cx;
+                parabola_pair(gp.first_order, s_vy[li - 2 * PW], s_vy[li - PW], s_vy[li], s_vy[li + PW],
+                              s_vy[li + 2 * PW], s_vy[li + 3 * PW], yv[o], yv[o + TX]);
+                parabola_pair(gp.first_order, s_p[li - 2 * PW], s_p[li - PW], s_p[li], s_p[li + PW],
+                              s_p[li + 2 * PW], s_p[li + 3 * PW], yp[o], yp[o + TX]);
             }
         }
         __syncthreads();
