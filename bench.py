@@ -265,6 +265,33 @@ def run_riemann_1d(seeds=range(16)):
             "zone_updates_per_s": zu / sec, "zone_updates": zu, "seconds": sec}
 
 
+def run_suite():
+    """The paper's test-suite workloads at their full sizes, each run to its
+    stop time with CFL steps (host-driven chunks of 64 steps): two blast
+    waves (1-D, 2400 cells, FP64, t = 0.038), Sedov (100^3, t = 0.05) and
+    Kelvin-Helmholtz (256^2, t = 1) in FP32 and FP64."""
+    import torch
+
+    from paper_1607_01105_amd import workloads as W
+    from paper_1607_01105_amd.ppml import Grid
+
+    out = {}
+    for name, prob, precs in (("blast_waves_2400", W.blast_waves(), ("fp64",)),
+                              ("sedov_100", W.sedov(100), ("fp32", "fp64")),
+                              ("kelvin_helmholtz_256", W.kelvin_helmholtz(256), ("fp32", "fp64"))):
+        out[name] = {}
+        for prec in precs:
+            g = Grid.from_problem(prob, prec=prec)
+            g.sync()
+            t0 = time.perf_counter()
+            t, _, n = g.run_to(prob.t_stop)
+            sec = time.perf_counter() - t0
+            out[name][prec] = {"steps": n, "t": t, "zone_updates_per_s": prob.cells * n / sec, "seconds": sec}
+            del g
+        torch.cuda.empty_cache()
+    return out
+
+
 def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -426,6 +453,8 @@ def main():
               f"fp64 {out['disk']['fp64']['zone_updates_per_s']:.3e} zu/s", file=sys.stderr, flush=True)
         print("[bench] 1-D Riemann configuration", file=sys.stderr, flush=True)
         out["riemann_1d"] = run_riemann_1d()
+        print("[bench] test-suite workloads", file=sys.stderr, flush=True)
+        out["suite"] = run_suite()
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob)

@@ -121,6 +121,56 @@ def shock_tube(k: int, n: int = 100, gamma: float = 1.4, cfl: float = 0.2) -> Pr
                          gamma, cfl, "outflow", t)
 
 
+def blast_waves(n: int = 2400, gamma: float = 1.4, cfl: float = 0.4, t_stop: float = 0.038) -> Problem:
+    """Two interacting blast waves (the paper's Colella-Woodward test): unit
+    density at rest on [0, 1], p = 1000 for x < 0.1, 0.01 for 0.1 < x < 0.9,
+    100 for x > 0.9, reflecting walls, 2400 cells.  The paper does not state
+    its output time; t = 0.038 is the time of the original test."""
+    x = (np.arange(n) + 0.5) / n
+    p = np.where(x < 0.1, 1000.0, np.where(x < 0.9, 0.01, 100.0)).reshape(1, 1, n)
+    rho = np.ones((1, 1, n))
+    z = np.zeros((1, 1, n))
+    return Problem(f"blast_waves_n{n}", 1, (n, 1, 1), (0.0, -0.5, -0.5), (1.0, 0.5, 0.5), gamma, cfl,
+                   [("reflect", "reflect"), ("periodic", "periodic"), ("periodic", "periodic")],
+                   rho, z.copy(), z.copy(), z.copy(), p, None, None, t_stop)
+
+
+def sedov(n: int = 100, gamma: float = 5.0 / 3.0, cfl: float = 0.3, e0: float = 0.6, r0: float = 0.02,
+          p_bg: float = 1e-5, t_stop: float = 0.05) -> Problem:
+    """Sedov blast (the paper's test): [-1/2, 1/2]^3, rho = 1, p = 1e-5, the
+    thermal energy E0 = 0.6 put into the cells whose centres lie within
+    r = 0.02 of the centre (at least the 8 central cells: at 100^3 the sphere
+    is about two cells wide), periodic boundaries (the shock stays inside
+    the box until t = 0.05)."""
+    n3, lo, hi = _grid(3, (n, n, n), (-0.5,) * 3, (0.5,) * 3)
+    X, Y, Z = _mesh(n3, lo, hi)
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    h = 1.0 / n
+    inside = r <= max(r0, math.sqrt(3.0) * h / 2 * 1.0000001)
+    vol = float(np.count_nonzero(inside)) * h ** 3
+    p = np.full(n3[::-1], p_bg)
+    p[inside] = (gamma - 1.0) * e0 / vol
+    rho = np.ones(n3[::-1])
+    zero = np.zeros(n3[::-1])
+    return Problem(f"sedov_n{n}", 3, n3, lo, hi, gamma, cfl, [("periodic", "periodic")] * 3, rho, zero.copy(),
+                   zero.copy(), zero.copy(), p, None, None, t_stop)
+
+
+def kelvin_helmholtz(n: int = 256, gamma: float = 1.4, cfl: float = 0.4, t_stop: float = 1.0) -> Problem:
+    """Kelvin-Helmholtz instability (the paper's test): [-1/2, 1/2]^2, p = 2.5,
+    rho = 2 and v_x = 0.5 where |y| <= 0.25 + 0.01 (1 + cos(8 pi x)), else
+    rho = 1 and v_x = -0.5; v_y = 0; periodic; 256^2."""
+    n3, lo, hi = _grid(2, (n, n), (-0.5, -0.5), (0.5, 0.5))
+    X, Y, Z = _mesh(n3, lo, hi)
+    inner = np.abs(Y) <= 0.25 + 0.01 * (1.0 + np.cos(8.0 * math.pi * X))
+    rho = np.where(inner, 2.0, 1.0)
+    vx = np.where(inner, 0.5, -0.5)
+    zero = np.zeros_like(rho)
+    p = np.full_like(rho, 2.5)
+    return Problem(f"kelvin_helmholtz_n{n}", 2, n3, lo, hi, gamma, cfl, [("periodic", "periodic")] * 3, rho, vx,
+                   zero.copy(), zero.copy(), p, None, None, t_stop)
+
+
 def _mode_set(kmax: float, ndim: int):
     r = int(math.floor(kmax))
     ks = []

@@ -560,4 +560,74 @@ def pin_outflow_exit_disturbance(lib=None, seeds=(0, 3)):
         assert d <= 0.01 * (abs(left[0] - right[0]) + 0.1), (seed, d)
 
 
-ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]
+def pin_blast_waves_printed(lib=None):
+    """Two interacting blast waves, 2400 cells, reflecting walls: at the
+    original test's time t = 0.038 the main shock sits near x = 0.76 with a
+    density of about 6.5 and the precursor near x = 0.86 has a density of
+    about 1.0 (numbers printed in the Colella-Woodward test section)."""
+    prob = W.blast_waves()
+    o = make_oracle(prob, lib=lib)
+    o.run(10 ** 7, t_stop=prob.t_stop)
+    rho = o.get("rho").ravel()
+    x = prob.centres(0)
+    i = int(np.argmax(rho))
+    assert abs(rho[i] - printed("blast_shock_rho")) <= 0.3, rho[i]
+    assert abs(x[i] - printed("blast_shock_x")) <= 0.02, x[i]
+    j = int(np.argmin(np.abs(x - printed("blast_precursor_x"))))
+    assert abs(rho[j] - printed("blast_precursor_rho")) <= 0.15, rho[j]
+    # mass is conserved between reflecting walls
+    assert abs(rho.sum() / prob.n[0] - 1.0) <= 1e-12
+
+
+def pin_sedov_shock_radius(lib=None, n=48):
+    """Sedov blast, E0 = 0.6 into rho = 1, gamma = 5/3: at t = 0.05 the
+    shell of maximum (angle-averaged) density lies within two cells behind
+    the similarity shock radius R = xi0 (E0 t^2 / rho)^(1/5), xi0 = 1.1517 for
+    gamma = 5/3 (Sedov's solution); total energy is conserved."""
+    prob = W.sedov(n)
+    o = make_oracle(prob, lib=lib)
+    e_before = o.totals()[4]
+    o.run(10 ** 6, t_stop=printed("sedov_t"))
+    rho = o.get("rho").reshape(prob.shape)
+    X, Y, Z = W._mesh(prob.n, prob.lo, prob.hi)
+    r = np.sqrt(X * X + Y * Y + Z * Z).ravel()
+    h = 1.0 / n
+    edges = np.arange(0.0, 0.5 + h, h / 2)
+    idx = np.digitize(r, edges)
+    prof = np.array([rho.ravel()[idx == j].mean() if np.any(idx == j) else 0.0 for j in range(1, len(edges))])
+    rc = 0.5 * (edges[1:] + edges[:-1])
+    r_peak = rc[int(np.argmax(prof))]
+    R = 1.1517 * (printed("sedov_e0") * printed("sedov_t") ** 2) ** 0.2
+    assert R - 2 * h <= r_peak <= R + 0.5 * h, (r_peak, R)
+    assert prof.max() > 1.8  # a compressed shell (4 in the strong-shock limit)
+    assert abs(o.totals()[4] - e_before) <= 1e-12 * e_before
+
+
+def pin_kelvin_helmholtz_growth(lib=None, n=128):
+    """Kelvin-Helmholtz setup of the paper at 128^2: the scheme lets the
+    instability grow -- the kinetic energy of v_y rises at least fivefold
+    between t = 0.1 and t = 0.3 and saturates (its maximum falls between
+    t = 0.3 and 0.6, the time scale tau_KH = 0.53 of the printed formula,
+    whose value is checked here too)."""
+    lam, rin, rout, vrel = 0.25, 2.0, 1.0, 1.0
+    tau = lam * (rin + rout) / (vrel * math.sqrt(rin * rout))
+    assert abs(tau - printed("kh_tau")) < 0.005
+    prob = W.kelvin_helmholtz(n)
+    o = make_oracle(prob, lib=lib)
+    ts = (0.1, 0.2, 0.3, 0.4, 0.5, 0.6)
+    ke = []
+    for t in ts:
+        o.run(10 ** 6, t_stop=t)
+        vy = o.get("my") / o.get("rho")
+        ke.append(float(np.mean(vy * vy)))
+    assert ke[2] >= 5.0 * ke[0], ke
+    assert 0.3 <= ts[int(np.argmax(ke))] <= 0.6, ke
+
+
+# the workload pins run full problems of the paper's test section: last, so
+# that a planted mistake is usually caught by a quick pin first
+for _p in (pin_blast_waves_printed, pin_sedov_shock_radius, pin_kelvin_helmholtz_growth):
+    _p.slow = True
+
+ALL_PINS = sorted((v for k, v in globals().items() if k.startswith("pin_")),
+                  key=lambda f: (getattr(f, "slow", False), f.__name__))

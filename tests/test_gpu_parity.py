@@ -432,3 +432,46 @@ def test_disk_full_size_one_step():
             print(f"disk full size {prec} field {f}: max rel err {err:.3e}", flush=True)
             assert err <= bound, (prec, f, err)
         del g
+
+
+# --------------------------------------------------------------------------
+# the paper's test-suite workloads (two blast waves, Sedov, Kelvin-Helmholtz)
+# --------------------------------------------------------------------------
+SUITE_SMALL = [
+    ("blast_waves_600", W.blast_waves(600, t_stop=0.01)),
+    ("sedov_24", W.sedov(24, t_stop=0.01)),
+    ("kelvin_helmholtz_64", W.kelvin_helmholtz(64, t_stop=0.05)),
+]
+
+
+@pytest.mark.parametrize("name,prob", SUITE_SMALL, ids=[c[0] for c in SUITE_SMALL])
+def test_suite_workloads_exact_bitwise(name, prob):
+    """Each run to its stop time with the GPU's own CFL steps: same step
+    count, same time and the oracle's bits (exact build)."""
+    o = make_oracle(prob)
+    taus = o.run(10 ** 6, t_stop=prob.t_stop)
+    g = _grid(prob, exact=True)
+    t, dt, steps = g.run_to(prob.t_stop)
+    assert steps == len(taus) and t == o.t, (steps, len(taus), t, o.t)
+    _assert_bitwise(g, o, prob.ndim, name)
+
+
+@pytest.mark.parametrize("name,prob,nsteps", [("kelvin_helmholtz_256", W.kelvin_helmholtz(256), 40),
+                                              ("sedov_100", W.sedov(100), 8),
+                                              ("blast_waves_2400", W.blast_waves(), 400)],
+                         ids=["kh256", "sedov100", "blast2400"])
+def test_suite_full_size_fp64_and_fp32(name, prob, nsteps):
+    """Full-size workloads driven with the oracle's steps: FP64 product build
+    within 1e-12, FP32 within 1e-4 L1 on density."""
+    o = make_oracle(prob)
+    taus = o.run(nsteps)
+    for prec in ("fp64", "fp32"):
+        g = _grid(prob, prec=prec)
+        for tau in taus:
+            g.step(1, dt_fixed=float(tau))
+        if prec == "fp64":
+            _assert_close(g, o, prob.ndim, 1e-12, name)
+        else:
+            r32, r64 = g.get("rho"), o.get("rho")
+            l1 = float(np.sum(np.abs(r32 - r64)) / np.sum(np.abs(r64)))
+            assert l1 <= 1e-4, (name, l1)
