@@ -51,11 +51,14 @@ typedef enum {
 
 typedef enum { PPML_FP32 = 0, PPML_FP64 = 1 } ppml_precision;
 
-/* Boundary conditions (the paper names periodic, outflow and reflecting
- * walls in its tests; their ghost-cell form is a reading: periodic = wrap,
- * outflow = copy of the nearest interior cell, reflect = mirror image with
- * the wall-normal momentum negated; three ghost layers per side). */
-typedef enum { PPML_PERIODIC = 0, PPML_OUTFLOW = 1, PPML_REFLECT = 2 } ppml_bc;
+/* Boundary conditions (the paper names periodic, outflow, reflecting and
+ * inflow boundaries in its tests; their ghost-cell form is a reading:
+ * periodic = wrap, outflow = copy of the nearest interior cell, reflect =
+ * mirror image with the wall-normal momentum negated, inflow = the prescribed
+ * state of the face (ppml_desc.inflow) in every ghost cell; three ghost layers
+ * per side, filled axis by axis x, y, z, so a cell that is a ghost along
+ * several axes follows the last of them). */
+typedef enum { PPML_PERIODIC = 0, PPML_OUTFLOW = 1, PPML_REFLECT = 2, PPML_INFLOW = 3 } ppml_bc;
 
 /* Conserved fields (Sec. 2, eqs. (1)-(4)). */
 typedef enum { PPML_RHO = 0, PPML_MX = 1, PPML_MY = 2, PPML_MZ = 3, PPML_ETOT = 4, PPML_EINT = 5 } ppml_field;
@@ -90,6 +93,9 @@ typedef struct {
                               the list of ppml_tile_shape (0 = default); changes
                               the speed only, never the results                  */
     int32_t reserved;      /* must be 0                                             */
+    double inflow[6][5];   /* ghost state (rho, vx, vy, vz, p) of face 2*axis+side
+                              (side 0 low, 1 high) where that face is PPML_INFLOW;
+                              rho, p > 0; converted like ppml_set_primitive   */
 } ppml_desc;
 
 /* Work-group tile shapes of the stage kernels for grids of ndim dimensions:

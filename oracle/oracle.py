@@ -19,7 +19,7 @@ _SRC = os.path.join(_HERE, "ppml_oracle.c")
 _LIB = os.path.join(_HERE, "libppml_oracle.so")
 
 FIELDS = ("rho", "mx", "my", "mz", "Et", "e")
-BC = {"periodic": 0, "outflow": 1, "reflect": 2}
+BC = {"periodic": 0, "outflow": 1, "reflect": 2, "inflow": 3}
 POT = {None: 0, "none": 0, "log": 1, "uniform": 2}
 
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-std=c11"]
@@ -56,6 +56,8 @@ def load_library(path: str | None = None) -> C.CDLL:
     lib.og_create.argtypes = [C.c_int, lp, dp, dp, C.c_double, C.c_double, ip, ip, C.c_double, C.c_int, dp, C.c_int]
     lib.og_destroy.argtypes = [C.c_void_p]
     lib.og_set_primitive.argtypes = [C.c_void_p, dp, dp, dp, dp, dp]
+    lib.og_set_inflow.restype = None
+    lib.og_set_inflow.argtypes = [C.c_void_p, C.c_int] + [C.c_double] * 5
     lib.og_set_conserved.argtypes = [C.c_void_p, C.POINTER(dp), C.c_double, C.c_double]
     lib.og_get.argtypes = [C.c_void_p, C.c_int, dp]
     lib.og_totals.argtypes = [C.c_void_p, dp]
@@ -127,11 +129,13 @@ class Oracle:
 
     ``n`` is (nx[, ny[, nz]]); ``lo``/``hi`` the domain extents per axis;
     ``bc`` a boundary name or a per-axis list of (lo, hi) names;
-    ``potential`` None, ("log", v0, rc, q, cx, cy, cz) or ("uniform", gx, gy, gz).
+    ``potential`` None, ("log", v0, rc, q, cx, cy, cz) or ("uniform", gx, gy, gz);
+    ``inflow`` maps a face (2 * axis + side, side 0 low / 1 high) with an
+    "inflow" boundary to its ghost state (rho, vx, vy, vz, p).
     """
 
     def __init__(self, ndim, n, lo, hi, gamma, cfl, bc="periodic", vacuum_ratio=1e-5,
-                 potential=None, first_order=False, lib: C.CDLL | str | None = None):
+                 potential=None, first_order=False, lib: C.CDLL | str | None = None, inflow=None):
         self.lib = lib if isinstance(lib, C.CDLL) else load_library(lib)
         self.ndim = int(ndim)
         n = list(n) + [1] * (3 - len(n))
@@ -159,6 +163,8 @@ class Oracle:
             float(gamma), float(cfl), blo, bhi, float(vacuum_ratio), kind, _dp(pot), int(bool(first_order)))
         if not self.g:
             raise ValueError("og_create failed")
+        for face, st in (inflow or {}).items():
+            self.lib.og_set_inflow(self.g, int(face), *[float(v) for v in st])
 
     def __del__(self):
         g = getattr(self, "g", None)

@@ -43,7 +43,7 @@
 
 #define NF 6
 enum { F_RHO = 0, F_MX = 1, F_MY = 2, F_MZ = 3, F_ET = 4, F_E = 5 };
-enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2 };
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2, BC_INFLOW = 3 };
 enum { POT_NONE = 0, POT_LOG = 1, POT_UNIFORM = 2 };
 #define GH 3 /* ghost layers on each side of an active axis */
 
@@ -58,6 +58,8 @@ typedef struct {
     int potential;
     double pot[8]; /* POT_LOG: v0, rc, q, cx, cy, cz ; POT_UNIFORM: gx, gy, gz */
     int first_order; /* 1: piecewise-constant states instead of parabolas */
+    double inflow[6][NF]; /* conserved state of the ghost cells of inflow face
+                             2*axis + side (0 low, 1 high)                 */
     double t;
     long steps;
     double *U[NF];   /* state U^n, ghosted                                 */
@@ -156,12 +158,14 @@ static long ghost_src(long i, long G, long n, int bc_lo, int bc_hi, int *flip)
     if (i < G) {
         if (bc_lo == BC_PERIODIC) return G + ((((i - G) % n) + n) % n);
         if (bc_lo == BC_OUTFLOW) return G;
+        if (bc_lo == BC_INFLOW) return -1; /* prescribed state */
         *flip = 1;
         return 2 * G - 1 - i; /* mirror */
     }
     if (i >= G + n) {
         if (bc_hi == BC_PERIODIC) return G + ((((i - G) % n) + n) % n);
         if (bc_hi == BC_OUTFLOW) return G + n - 1;
+        if (bc_hi == BC_INFLOW) return -1;
         *flip = 1;
         return 2 * (G + n) - 1 - i;
     }
@@ -171,7 +175,8 @@ static long ghost_src(long i, long G, long n, int bc_lo, int bc_hi, int *flip)
 /* Fill the ghost layers of V, axis by axis (x, then y, then z), each pass over
  * the full extent of the other axes so that edges and corners are filled.
  * Periodic: wrap; outflow: copy the nearest interior cell; reflect: mirror
- * and negate the momentum normal to the wall. */
+ * and negate the momentum normal to the wall; inflow: the prescribed state
+ * (the same in both stages). */
 static void fill_ghosts(og_grid *g, double **V)
 {
     for (int a = 0; a < 3; a++) {
@@ -190,6 +195,11 @@ static void fill_ghosts(og_grid *g, double **V)
                     if (i >= G && i < G + n) continue;
                     int flip;
                     long src = ghost_src(i, G, n, g->bc_lo[a], g->bc_hi[a], &flip);
+                    if (src < 0) {
+                        const double *st = g->inflow[2 * a + (i >= G + n ? 1 : 0)];
+                        for (int f = 0; f < NF; f++) V[f][base + i * s] = st[f];
+                        continue;
+                    }
                     for (int f = 0; f < NF; f++) V[f][base + i * s] = V[f][base + src * s];
                     if (flip) V[F_MX + a][base + i * s] = -V[F_MX + a][base + i * s];
                 }
@@ -279,6 +289,25 @@ void og_set_primitive(og_grid *g, const double *rho, const double *vx, const dou
     compute_rho_mean0(g);
     g->t = 0.0;
     g->steps = 0;
+}
+
+/* State of the ghost cells of an inflow face (face = 2*axis + side, side 0
+ * low, 1 high) from primitives, with the conversion of og_set_primitive. */
+void og_set_inflow(og_grid *g, int face, double rho, double vx, double vy, double vz, double p)
+{
+    if (face < 0 || face >= 6) return;
+    double ux = vx;
+    double uy = g->ndim >= 2 ? vy : 0.0;
+    double uz = g->ndim >= 3 ? vz : 0.0;
+    double e = p / (g->gamma - 1.0);
+    double ke = 0.5 * rho * (ux * ux + uy * uy + uz * uz);
+    double *st = g->inflow[face];
+    st[F_RHO] = rho;
+    st[F_MX] = rho * ux;
+    st[F_MY] = rho * uy;
+    st[F_MZ] = rho * uz;
+    st[F_ET] = e + ke;
+    st[F_E] = e;
 }
 
 /* Conserved fields directly (checkpoint restore); f[6] interior arrays. */

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -91,9 +92,16 @@ int validate(const ppml_desc *d)
             if (!(d->hi[a] > d->lo[a])) return fail(PPML_EINVAL, "hi[%d] must exceed lo[%d]", a, a);
             for (int s = 0; s < 2; s++) {
                 int b = s ? d->bc_hi[a] : d->bc_lo[a];
-                if (b != PPML_PERIODIC && b != PPML_OUTFLOW && b != PPML_REFLECT)
+                if (b != PPML_PERIODIC && b != PPML_OUTFLOW && b != PPML_REFLECT && b != PPML_INFLOW)
                     return fail(PPML_EINVAL, "bad boundary code on axis %d", a);
                 if (b == PPML_REFLECT && d->n[a] < 3) return fail(PPML_EINVAL, "reflecting axis %d needs n >= 3", a);
+                if (b == PPML_INFLOW) {
+                    const double *st = d->inflow[2 * a + s];
+                    for (int q = 0; q < 5; q++)
+                        if (!std::isfinite(st[q])) return fail(PPML_EINVAL, "inflow state of face %d is not finite", 2 * a + s);
+                    if (!(st[0] > 0.0) || !(st[4] > 0.0))
+                        return fail(PPML_EINVAL, "inflow face %d needs rho > 0 and p > 0", 2 * a + s);
+                }
             }
             if ((d->bc_lo[a] == PPML_PERIODIC) != (d->bc_hi[a] == PPML_PERIODIC))
                 return fail(PPML_EINVAL, "axis %d: periodic must be set on both faces", a);
@@ -386,6 +394,37 @@ int ppml_create(const ppml_desc *d, void *state_dev, void *scratch_dev, void *hi
     gp.first_order = (d->flags & PPML_FLAG_FIRST_ORDER) ? 1 : 0;
     for (int i = 0; i < 8; i++) gp.pot[i] = d->pot[i];
     set_tiling(gp, d->ndim, d->tile);
+    // conserved ghost states of inflow faces, converted in FP64 as the state
+    // is, into the control block
+    double tab[6][6];
+    memset(tab, 0, sizeof tab);
+    gp.any_inflow = 0;
+    for (int a = 0; a < d->ndim; a++)
+        for (int s = 0; s < 2; s++) {
+            if ((s ? d->bc_hi[a] : d->bc_lo[a]) != PPML_INFLOW) continue;
+            const double *st = d->inflow[2 * a + s];
+            const double r = st[0];
+            const double ux = st[1];
+            const double uy = d->ndim >= 2 ? st[2] : 0.0;
+            const double uz = d->ndim >= 3 ? st[3] : 0.0;
+            const double e = st[4] / (d->gamma - 1.0);
+            const double ke = 0.5 * r * (ux * ux + uy * uy + uz * uz);
+            double *c = tab[2 * a + s];
+            c[0] = r;
+            c[1] = r * ux;
+            c[2] = r * uy;
+            c[3] = r * uz;
+            c[4] = e + ke;
+            c[5] = e;
+            gp.any_inflow = 1;
+        }
+    if (gp.any_inflow) {
+        hipError_t e = hipMemcpy((char *)g->ctrl + offsetof(Ctrl, inflow), tab, sizeof tab, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            delete g;
+            return fail(PPML_EHIP, "inflow states: %s", hipGetErrorString(e));
+        }
+    }
     g->gpE = gp;
     g->gpL = gp;
     if (d->ndim == 3) {

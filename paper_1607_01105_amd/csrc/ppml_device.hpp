@@ -17,7 +17,7 @@
 
 namespace ppml {
 
-enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2 };
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2, BC_INFLOW = 3 };
 enum { POT_NONE = 0, POT_LOG = 1, POT_UNIFORM = 2 };
 constexpr int GH = 3;  // ghost layers: a cell update reads q[i-3 .. i+3]
 
@@ -37,6 +37,7 @@ struct GridParams {
     int first_order;  // 1: piecewise-constant states (first-order scheme of Sec. 2.1)
     int tiles[3];  // work-group tiles along x, y and z chunks of the stage kernels
     int cz;        // planes per z chunk (3-D)
+    int any_inflow;  // some face has an inflow boundary (states in Ctrl::inflow)
 };
 
 // Device control block of one grid (lives in the scratch area).  Every
@@ -60,6 +61,7 @@ struct Ctrl {
     int slot_cur;         // slot holding the maxima of the current state
     int slot_l;           // slot_cur of the step in flight (for the Lagrangian kernel)
     int pad;
+    double inflow[6][6];  // conserved ghost state of inflow face 2*axis+side (set once)
 };
 
 #ifdef PPML_EXACT
@@ -97,19 +99,51 @@ __device__ __forceinline__ int map_index(int i, int n, int bclo, int bchi, int &
             int r = i % n;
             return r < 0 ? r + n : r;
         }
-        if (bclo == BC_OUTFLOW) return 0;
+        if (bclo == BC_OUTFLOW || bclo == BC_INFLOW) return 0;  // inflow: value replaced
         flip = 1;
         int r = -1 - i;
         return r < n ? r : n - 1;
     }
     if (i >= n) {
         if (bchi == BC_PERIODIC) return i % n;
-        if (bchi == BC_OUTFLOW) return n - 1;
+        if (bchi == BC_OUTFLOW || bchi == BC_INFLOW) return n - 1;
         flip = 1;
         int r = 2 * n - 1 - i;
         return r >= 0 ? r : 0;
     }
     return i;
+}
+
+// Inflow face (2*axis + side) whose prescribed state the ghost index i takes
+// along an axis, or -1.  Ghost layers are filled axis by axis (x, y, z), so a
+// cell that is a ghost along several axes takes the state of the last inflow
+// axis, with the wall-normal momentum of later reflecting axes negated.
+__device__ __forceinline__ int inflow_face(int i, int n, int bclo, int bchi, int axis)
+{
+    if (i < 0 && bclo == BC_INFLOW) return 2 * axis;
+    if (i >= n && bchi == BC_INFLOW) return 2 * axis + 1;
+    return -1;
+}
+
+// Component q (0 rho, 1-3 rho v_x..z, 4 rho E, 5 rho eps) of the prescribed
+// state of inflow face `face` (read from the control block only on the rare
+// ghost cells of inflow faces).
+template <typename T> __device__ __forceinline__ T inflow_value(const Ctrl *ctrl, int face, int q)
+{
+    return (T)ctrl->inflow[face][q];
+}
+
+// Component of the inflow state for stored field f of a grid of NDIM
+// dimensions (fields rho, rho v_0 .. rho v_{NDIM-1}, rho E, rho eps).
+template <int NDIM> __device__ __forceinline__ int inflow_component(int f) { return f <= NDIM ? f : f + (3 - NDIM); }
+
+// Inflow code of a staged cell (x, y of a plane): 0 none, else 1 + the face
+// of the last inflow axis among x and y.
+__device__ __forceinline__ unsigned inflow_code_xy(const GridParams &gp, int i, int j, int ndim)
+{
+    const int fx = inflow_face(i, gp.n[0], gp.bc_lo[0], gp.bc_hi[0], 0);
+    const int fy = ndim >= 2 ? inflow_face(j, gp.n[1], gp.bc_lo[1], gp.bc_hi[1], 1) : -1;
+    return fy >= 0 ? (unsigned)(fy + 1) : (fx >= 0 ? (unsigned)(fx + 1) : 0u);
 }
 
 // Appendix step 1: limited slope delta_m q of the middle value.

@@ -276,7 +276,7 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
     // momentum flips, two bits per cell.  Only the plane index changes along
     // z, so the maps are evaluated once.
     constexpr int RC = (PS + NT - 1) / NT;
-    static_assert(2 * RC <= 32, "flip bits");
+    static_assert(2 * RC <= 16 && 16 + 3 * RC <= 32, "flip and inflow bits");
     int ccode[RC];
     unsigned flips = 0;
 #pragma unroll
@@ -291,6 +291,7 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
                 const int ay = NDIM >= 2 ? map_index(y0 + dy, ny, gp.bc_lo[1], gp.bc_hi[1], fy) : 0;
                 ccode[r] = ay * nx + ax;
                 flips |= (unsigned)(fx | (fy << 1)) << (2 * r);
+                if (gp.any_inflow) flips |= inflow_code_xy(gp, x0 + dx, y0 + dy, NDIM) << (16 + 3 * r);
             }
         }
     }
@@ -314,10 +315,18 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
             int fz;
             const int mz = map_index(m, nz, gp.bc_lo[2], gp.bc_hi[2], fz);
             const int c = mz * plane + cy_ * nx + cx_;
-            const T rho = Uf[0][c];
+            T rho = Uf[0][c];
             T mzv = Uf[3][c];
             if (fz) mzv = -mzv;
-            const T e = Uf[5][c];
+            T e = Uf[5][c];
+            if (gp.any_inflow) {  // plane m is a ghost of an inflow z face
+                const int fzi = inflow_face(m, nz, gp.bc_lo[2], gp.bc_hi[2], 2);
+                if (fzi >= 0) {
+                    rho = inflow_value<T>(ctrl, fzi, 0);
+                    mzv = inflow_value<T>(ctrl, fzi, 3);
+                    e = inflow_value<T>(ctrl, fzi, 5);
+                }
+            }
             const T vz = mzv / rho;
             const T p = gm1 * e;
             const T s = dsqrt(rho);
@@ -388,6 +397,41 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
             s_s[li] = s;
             s_r32[li] = rho * s;
             s_ps[li] = p * s;
+        }
+        if (gp.any_inflow) {
+            // ghosts of inflow faces take the face's state (a y face comes
+            // after any x reflection, so only later flips apply)
+#pragma unroll
+            for (int r = 0; r < RC; r++) {
+                const unsigned io = (flips >> (16 + 3 * r)) & 7u;
+                if (ccode[r] < 0 || io == 0) continue;
+                const int li = tid + r * NT;
+                const unsigned fl = io >= 3 ? 0u : (flips >> (2 * r)) & 2u;
+                const T rho = inflow_value<T>(ctrl, io - 1, 0);
+                const T e = inflow_value<T>(ctrl, io - 1, 5);
+                const T mxv = inflow_value<T>(ctrl, io - 1, 1);
+#ifdef PPML_EXACT
+                s_vx[li] = mxv / rho;
+#else
+                const T ir = T(1) / rho;
+                s_vx[li] = mxv * ir;
+#endif
+                if constexpr (NDIM >= 2) {
+                    T myv = inflow_value<T>(ctrl, io - 1, 2);
+                    if (fl & 2) myv = -myv;
+#ifdef PPML_EXACT
+                    s_vy[li] = myv / rho;
+#else
+                    s_vy[li] = myv * ir;
+#endif
+                }
+                const T p = gm1 * e;
+                const T s = dsqrt(rho);
+                s_p[li] = p;
+                s_s[li] = s;
+                s_r32[li] = rho * s;
+                s_ps[li] = p * s;
+            }
         }
         __syncthreads();
         // parabolas of v_d and p, two neighbouring cells per job (shared slopes
@@ -594,12 +638,13 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
     const int own_off = cy_ * nx + cx_;
 
     // Tile cells this thread stages on every plane: the (y, x) offset of the
-    // boundary-mapped source cell (-1 where nothing is loaded) and the
-    // momentum flips, two bits per cell (x, y).  Only the plane index changes
+    // boundary-mapped source cell (-1 where nothing is loaded), the momentum
+    // flips, two bits per cell (x, y) from bit 0, and the inflow code of the
+    // cell, three bits per cell from bit 16.  Only the plane index changes
     // along z, so the maps are evaluated once.
     constexpr int RC = (PS + NT - 1) / NT;
     constexpr int RV = (VS + NT - 1) / NT;
-    static_assert(2 * (RC + RV) <= 32, "flip bits");
+    static_assert(2 * (RC + RV) <= 16 && 16 + 3 * (RC + RV) <= 32, "flip and inflow bits");
     int ccode[RC], vcode[RV];
     unsigned flips = 0;
 #pragma unroll
@@ -614,6 +659,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                 const int ay = NDIM >= 2 ? map_index(y0 + dy, ny, gp.bc_lo[1], gp.bc_hi[1], fy) : 0;
                 ccode[r] = ay * nx + ax;
                 flips |= (unsigned)(fx | (fy << 1)) << (2 * r);
+                if (gp.any_inflow) flips |= inflow_code_xy(gp, x0 + dx, y0 + dy, NDIM) << (16 + 3 * r);
             }
         }
     }
@@ -627,6 +673,8 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
             const int ay = NDIM >= 2 ? map_index(y0 + li / VW - 1, ny, gp.bc_lo[1], gp.bc_hi[1], fy) : 0;
             vcode[r] = ay * nx + ax;
             flips |= (unsigned)(fx | (fy << 1)) << (2 * (RC + r));
+            if (gp.any_inflow)
+                flips |= inflow_code_xy(gp, x0 + li % VW - 1, y0 + li / VW - 1, NDIM) << (16 + 3 * (RC + r));
         }
     }
 
@@ -681,6 +729,14 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
             const int c = mz * plane + own_off;
 #pragma unroll
             for (int f = 0; f < NF; f++) ov[f] = Wf[f][c];
+            if (gp.any_inflow) {  // plane m is a ghost of an inflow z face
+                const int fzi = inflow_face(m, nz, gp.bc_lo[2], gp.bc_hi[2], 2);
+                if (fzi >= 0) {
+#pragma unroll
+                    for (int f = 0; f < NF; f++) ov[f] = inflow_value<T>(ctrl, fzi, inflow_component<NDIM>(f));
+                    fzo = 0;
+                }
+            }
         }
 
         // velocity plane needed by this iteration (3-D: plane m-2; else plane 0)
@@ -731,6 +787,47 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
 #else
                     s_vz[zslot][li] = mzv * ir;
 #endif
+                }
+            }
+            if (gp.any_inflow) {
+                // ghosts of inflow faces take the face's state: a z face (the
+                // last axis filled) overrides x and y; after an x or y face
+                // only the later reflections (y, z) apply
+                const int fzi = NDIM == 3 ? inflow_face(vpl, nz, gp.bc_lo[2], gp.bc_hi[2], 2) : -1;
+#pragma unroll 1
+                for (int r = 0; r < RV; r++) {
+                    const unsigned io = (flips >> (16 + 3 * (RC + r))) & 7u;
+                    if (vcode[r] < 0 || (io == 0 && fzi < 0)) continue;
+                    const int li = tid + r * NT;
+                    const int face = fzi >= 0 ? fzi : (int)io - 1;
+                    const unsigned fl = fzi >= 0 ? 0u : (io >= 3 ? 0u : (flips >> (2 * (RC + r))) & 2u);
+                    const bool flz = fzi < 0 && fz;
+                    const T rho = inflow_value<T>(ctrl, face, 0);
+                    const T mxv = inflow_value<T>(ctrl, face, 1);
+#ifdef PPML_EXACT
+                    s_vx[slot][li] = mxv / rho;
+#else
+                    const T ir = T(1) / rho;
+                    s_vx[slot][li] = mxv * ir;
+#endif
+                    if constexpr (NDIM >= 2) {
+                        T myv = inflow_value<T>(ctrl, face, 2);
+                        if (fl & 2) myv = -myv;
+#ifdef PPML_EXACT
+                        s_vy[slot][li] = myv / rho;
+#else
+                        s_vy[slot][li] = myv * ir;
+#endif
+                    }
+                    if constexpr (NDIM == 3) {
+                        T mzv = inflow_value<T>(ctrl, face, 3);
+                        if (flz) mzv = -mzv;
+#ifdef PPML_EXACT
+                        s_vz[zslot][li] = mzv / rho;
+#else
+                        s_vz[zslot][li] = mzv * ir;
+#endif
+                    }
                 }
             }
         }
@@ -805,7 +902,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                 // wait for this wave's transfers, then mirror the normal
                 // momenta at reflecting faces
                 __builtin_amdgcn_s_waitcnt(VMCNT0);
-                if (flips) {
+                if (flips & 0xFFFFu) {
 #pragma unroll
                     for (int r = 0; r < RC; r++) {
                         if (ccode[r] < 0) continue;
@@ -813,6 +910,22 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                         const unsigned fl = flips >> (2 * r);
                         if (fl & 1) sf[1][li] = -sf[1][li];
                         if (NDIM >= 2 && (fl & 2)) sf[2][li] = -sf[2][li];
+                    }
+                }
+                if (gp.any_inflow) {
+                    // ghosts of inflow faces take the face's state (after an x
+                    // face only a y reflection applies)
+#pragma unroll 1
+                    for (int r = 0; r < RC; r++) {
+                        const unsigned io = (flips >> (16 + 3 * r)) & 7u;
+                        if (ccode[r] < 0 || io == 0) continue;
+                        const int li = tid + r * NT;
+                        const bool fly = io < 3 && ((flips >> (2 * r)) & 2u);
+#pragma unroll 1
+                        for (int f = 0; f < NF; f++) {
+                            const T v = inflow_value<T>(ctrl, io - 1, inflow_component<NDIM>(f));
+                            sf[f][li] = (f == 2 && fly) ? -v : v;
+                        }
                     }
                 }
             } else {
@@ -830,6 +943,25 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                         T v = Wf[f][c];
                         if ((f == 1 && (fl & 1)) || (NDIM >= 2 && f == 2 && (fl & 2))) v = -v;
                         sf[g][li] = v;
+                    }
+                }
+                if (gp.any_inflow) {
+                    // ghosts of inflow faces take the face's state (a y face
+                    // comes after any x reflection)
+#pragma unroll
+                    for (int r = 0; r < RC; r++) {
+                        const unsigned io = (flips >> (16 + 3 * r)) & 7u;
+                        if (ccode[r] < 0 || io == 0) continue;
+                        const int li = tid + r * NT;
+                        const unsigned fl = io >= 3 ? 0u : (flips >> (2 * r)) & 2u;
+#pragma unroll
+                        for (int g = 0; g < G; g++) {
+                            const int f = f0 + g;
+                            if (f >= NF) break;
+                            T v = inflow_value<T>(ctrl, io - 1, inflow_component<NDIM>(f));
+                            if (NDIM >= 2 && f == 2 && (fl & 2)) v = -v;
+                            sf[g][li] = v;
+                        }
                     }
                 }
             }

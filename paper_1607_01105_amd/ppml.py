@@ -18,12 +18,12 @@ LIB_EXACT_PATH = os.path.join(HERE, "csrc", "libppml_exact.so")
 
 PPML_OK, PPML_EINVAL, PPML_ENOMEM, PPML_EHIP, PPML_ENONFINITE, PPML_EBUDGET, PPML_ESTATE = 0, -1, -2, -3, -4, -5, -6
 PPML_FP32, PPML_FP64 = 0, 1
-PPML_PERIODIC, PPML_OUTFLOW, PPML_REFLECT = 0, 1, 2
+PPML_PERIODIC, PPML_OUTFLOW, PPML_REFLECT, PPML_INFLOW = 0, 1, 2, 3
 PPML_RHO, PPML_MX, PPML_MY, PPML_MZ, PPML_ETOT, PPML_EINT = 0, 1, 2, 3, 4, 5
 PPML_POT_NONE, PPML_POT_LOG, PPML_POT_UNIFORM = 0, 1, 2
 PPML_FLAG_FIRST_ORDER = 1
 
-BC = {"periodic": PPML_PERIODIC, "outflow": PPML_OUTFLOW, "reflect": PPML_REFLECT}
+BC = {"periodic": PPML_PERIODIC, "outflow": PPML_OUTFLOW, "reflect": PPML_REFLECT, "inflow": PPML_INFLOW}
 PREC = {"fp32": PPML_FP32, "f32": PPML_FP32, "fp64": PPML_FP64, "f64": PPML_FP64}
 POT = {None: PPML_POT_NONE, "none": PPML_POT_NONE, "log": PPML_POT_LOG, "uniform": PPML_POT_UNIFORM}
 
@@ -34,7 +34,7 @@ class ppml_desc(C.Structure):
         ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("gamma", C.c_double), ("cfl", C.c_double),
         ("bc_lo", C.c_int32 * 3), ("bc_hi", C.c_int32 * 3), ("vacuum_ratio", C.c_double),
         ("potential", C.c_int32), ("flags", C.c_int32), ("pot", C.c_double * 8),
-        ("tile", C.c_int32), ("reserved", C.c_int32),
+        ("tile", C.c_int32), ("reserved", C.c_int32), ("inflow", (C.c_double * 5) * 6),
     ]
 
 
@@ -114,7 +114,7 @@ def _check(lib, rc):
 
 
 def make_desc(ndim, n, lo, hi, gamma, cfl, bc="periodic", prec="fp64", vacuum_ratio=1e-5, potential=None,
-              first_order=False, tile=0):
+              first_order=False, tile=0, inflow=None):
     d = ppml_desc()
     d.ndim = int(ndim)
     d.prec = PREC[prec] if isinstance(prec, str) else int(prec)
@@ -139,6 +139,9 @@ def make_desc(ndim, n, lo, hi, gamma, cfl, bc="periodic", prec="fp64", vacuum_ra
     d.flags = PPML_FLAG_FIRST_ORDER if first_order else 0
     d.tile = int(tile)
     d.reserved = 0
+    for face, st in (inflow or {}).items():  # face 2*axis+side -> (rho, vx, vy, vz, p)
+        for q in range(5):
+            d.inflow[int(face)][q] = float(st[q])
     if potential:
         for i, v in enumerate(potential[1:]):
             d.pot[i] = float(v)
@@ -194,11 +197,13 @@ class Grid:
     """One grid on the current GPU; state and scratch are torch tensors."""
 
     def __init__(self, ndim, n, lo, hi, gamma, cfl, bc="periodic", prec="fp64", vacuum_ratio=1e-5,
-                 potential=None, device="cuda", stream=None, exact=False, first_order=False, lib_path=None, tile=0):
+                 potential=None, device="cuda", stream=None, exact=False, first_order=False, lib_path=None, tile=0,
+                 inflow=None):
         import torch
 
         self.lib = load(lib_path or (LIB_EXACT_PATH if exact else LIB_PATH))
-        self.desc = make_desc(ndim, n, lo, hi, gamma, cfl, bc, prec, vacuum_ratio, potential, first_order, tile)
+        self.desc = make_desc(ndim, n, lo, hi, gamma, cfl, bc, prec, vacuum_ratio, potential, first_order, tile,
+                              inflow)
         self.ndim = int(ndim)
         self.ncell = int(self.desc.n[0] * self.desc.n[1] * self.desc.n[2])
         sb = ppml_state_bytes(self.desc, self.lib)
@@ -214,6 +219,7 @@ class Grid:
 
     @classmethod
     def from_problem(cls, prob, prec="fp64", exact=False, vacuum_ratio=1e-5, **kw):
+        kw.setdefault("inflow", getattr(prob, "inflow", None))
         g = cls(prob.ndim, prob.n, prob.lo, prob.hi, prob.gamma, prob.cfl, bc=prob.bc, prec=prec,
                 vacuum_ratio=vacuum_ratio, potential=prob.potential, exact=exact, **kw)
         g.set_primitive(prob.rho, prob.vx, prob.vy, prob.vz, prob.p)

@@ -39,7 +39,7 @@ class Problem:
     hi: tuple
     gamma: float
     cfl: float
-    bc: list            # per axis (lo, hi) names: "periodic" | "outflow" | "reflect"
+    bc: list            # per axis (lo, hi) names: "periodic" | "outflow" | "reflect" | "inflow"
     rho: np.ndarray
     vx: np.ndarray
     vy: np.ndarray
@@ -48,6 +48,7 @@ class Problem:
     potential: tuple | None = None   # ("log", v0, rc, q, cx, cy, cz) | ("uniform", gx, gy, gz)
     nsteps: int | None = None
     t_stop: float | None = None
+    inflow: dict | None = None       # face (2 * axis + side) -> ghost state (rho, vx, vy, vz, p)
 
     @property
     def shape(self):
@@ -302,6 +303,33 @@ def uniform(ndim: int, n: int | tuple, rho0=1.0, v0=(0.3, -0.2, 0.1), p0=0.7, ga
     return Problem(f"uniform{ndim}d", ndim, n3, lo, hi, gamma, cfl, [(bc, bc)] * 3, rho0 * ones,
                    v0[0] * ones, (v0[1] if ndim >= 2 else 0.0) * ones, (v0[2] if ndim >= 3 else 0.0) * ones,
                    p0 * ones, None, None, None)
+
+
+def supersonic_inflow(n: int = 400, left=(1.0, 3.0, 1.0), right=(0.5, 3.0, 0.4), gamma: float = 1.4,
+                      cfl: float = 0.4, t_stop: float = 0.1) -> Problem:
+    """1-D gas moving at Mach ~4 through [0, 1]: the interior holds the right
+    state (rho, u, p), the inflow face at x = 0 feeds the left state, outflow
+    at x = 1.  Every wave of the Riemann problem between the two states moves
+    to the right, so on [0, 1] the solution is that Riemann problem's, with
+    the discontinuity starting at x = 0."""
+    x = (np.arange(n) + 0.5) / n
+    shp = (1, 1, n)
+    z = np.zeros(shp)
+    return Problem(f"supersonic_inflow_n{n}", 1, (n, 1, 1), (0.0, -0.5, -0.5), (1.0, 0.5, 0.5), gamma, cfl,
+                   [("inflow", "outflow"), ("periodic", "periodic"), ("periodic", "periodic")],
+                   np.full(shp, right[0]), np.full(shp, right[1]), z.copy(), z.copy(), np.full(shp, right[2]),
+                   None, None, t_stop, {0: (left[0], left[1], 0.0, 0.0, left[2])})
+
+
+def inflow_channel(ndim: int, n: int | tuple, seed: int, gamma: float = 1.4, cfl: float = 0.4) -> Problem:
+    """Inflow at x = 0 (a fixed supersonic stream) into random blocks, outflow
+    at x = 1, reflecting walls on the other axes: a wind tunnel without an
+    obstacle.  The inflow state differs from every interior state."""
+    p = blocks(ndim, n, seed, gamma=gamma, cfl=cfl)
+    p.name = f"inflow_channel{ndim}d"
+    p.bc = [("inflow", "outflow")] + [("reflect", "reflect")] * (ndim - 1) + [("periodic", "periodic")] * (3 - ndim)
+    p.inflow = {0: (1.4, 3.0, 0.2 if ndim >= 2 else 0.0, -0.1 if ndim >= 3 else 0.0, 1.0)}
+    return p
 
 
 def random_smooth(ndim: int, n: int | tuple, seed: int, gamma=1.4, cfl=0.4, bc="periodic",

@@ -624,6 +624,44 @@ def pin_kelvin_helmholtz_growth(lib=None, n=128):
     assert 0.3 <= ts[int(np.argmax(ke))] <= 0.6, ke
 
 
+def pin_inflow_uniform_stream(lib=None):
+    """A uniform stream entering through an inflow face that carries the same
+    state (outflow opposite, reflecting or periodic walls elsewhere) stays
+    uniform: every field within a few ulps after 5 steps (the ghost rho*eps is
+    p/(gamma-1), the interior's the corrected value, which differ by rounding)."""
+    for ndim, n in ((1, 32), (2, 12), (3, 8)):
+        prob = W.uniform(ndim, n)
+        prob.bc = [("inflow", "outflow")] + [("periodic", "periodic")] * 2
+        prob.inflow = {0: (1.0, 0.3, -0.2, 0.1, 0.7)}
+        o = make_oracle(prob, lib=lib)
+        f0 = o.conserved()
+        o.run(5)
+        f1 = o.conserved()
+        for k in range(6):
+            scale = max(float(np.max(np.abs(f0[k]))), 1e-300)
+            assert np.max(np.abs(f1[k] - f0[k])) <= 1e-14 * scale, (ndim, k)
+
+
+def pin_supersonic_inflow_riemann(lib=None):
+    """Supersonic stream: the inflow face feeds the left state of a Riemann
+    problem whose waves all move right; on [0, 1] the solution converges to
+    the exact one (Toro's solver) and the cells next to the inflow face hold
+    the left state."""
+    errs = []
+    for n in (200, 400, 800):
+        prob = W.supersonic_inflow(n)
+        o = make_oracle(prob, lib=lib)
+        o.run(10 ** 6, t_stop=prob.t_stop)
+        left = (1.0, 3.0, 1.0)
+        right = (0.5, 3.0, 0.4)
+        assert er.sample(left, right, 1.4, 0.0)[0] == left[0]  # the leftmost wave moves right
+        ex = er.cell_averages(left, right, 1.4, 0.0, prob.t_stop, np.linspace(0.0, 1.0, n + 1), sub=8)
+        pr = o.primitive()
+        errs.append(l1(pr["rho"].ravel(), ex[0]))
+        assert abs(pr["rho"].ravel()[0] - left[0]) <= 1e-12 and abs(pr["vx"].ravel()[0] - left[1]) <= 1e-12
+    assert errs[2] < errs[1] < errs[0] and errs[2] < 5e-3, errs
+
+
 # the workload pins run full problems of the paper's test section: last, so
 # that a planted mistake is usually caught by a quick pin first
 for _p in (pin_blast_waves_printed, pin_sedov_shock_radius, pin_kelvin_helmholtz_growth):

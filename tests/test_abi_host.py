@@ -77,7 +77,10 @@ def test_state_and_scratch_bytes(lib):
 
 @pytest.mark.parametrize("bad", [dict(ndim=4), dict(gamma=1.0), dict(cfl=1.0), dict(cfl=0.0),
                                  dict(n=(0, 8, 4)), dict(hi=(0, 1, 1)), dict(bc="reflect", n=(2, 8, 4)),
-                                 dict(vacuum_ratio=-1.0), dict(tile=-1), dict(tile=99)])
+                                 dict(vacuum_ratio=-1.0), dict(tile=-1), dict(tile=99),
+                                 dict(bc=[("inflow", "outflow")] * 3, inflow={0: (-1.0, 0, 0, 0, 1.0)}),
+                                 dict(bc=[("inflow", "outflow")] * 3, inflow={0: (1.0, 0, 0, 0, 0.0)}),
+                                 dict(bc=[("inflow", "periodic")] * 3)])
 def test_invalid_descriptors_rejected(lib, bad):
     from paper_1607_01105_amd import ppml
 
@@ -143,3 +146,11 @@ def test_autotune_pick_prefers_fastest_then_default():
     assert pick({0: 1.0, 1: 0.5, 2: 0.7}) == 1
     assert pick({0: 0.5, 1: 0.5}) == 0
     assert pick({2: 0.3, 1: 0.3, 3: 0.9}) == 1
+
+
+def test_inflow_descriptor_accepted(lib):
+    from paper_1607_01105_amd import ppml
+
+    d = _desc(bc=[("inflow", "outflow"), ("reflect", "inflow"), ("outflow", "outflow")],
+              inflow={0: (1.0, 2.0, 0.0, 0.0, 1.0), 3: (0.5, 0.0, -1.0, 0.0, 0.2)})
+    assert ppml.ppml_state_bytes(d, lib) > 0

@@ -30,7 +30,10 @@ def _problems():
     p3.bc = [("reflect", "outflow"), ("periodic", "periodic"), ("outflow", "reflect")]
     p2 = W.blocks(2, (75, 37), seed=42, bc="reflect")
     p1 = W.riemann_1d(7)
-    return [("1d", p1), ("2d", p2), ("3d", p3)]
+    p4 = W.blocks(3, (37, 21, 19), seed=44)
+    p4.bc = [("inflow", "outflow"), ("reflect", "inflow"), ("inflow", "reflect")]
+    p4.inflow = {0: (1.4, 2.5, 0.3, -0.2, 1.0), 3: (0.8, 0.1, -1.5, 0.4, 0.6), 4: (1.1, -0.3, 0.2, 1.8, 0.9)}
+    return [("1d", p1), ("2d", p2), ("3d", p3), ("3d_inflow", p4)]
 
 
 @pytest.mark.parametrize("exact,prec", [(True, "fp64"), (False, "fp32")], ids=["exact_fp64", "fp32"])

@@ -69,6 +69,9 @@ MUTANTS = [
     ("cfl_h_max", "if (g->h[a] < h) h = g->h[a];", "if (g->h[a] > h) h = g->h[a];"),
     ("pressure_eos", "qp[m] = (gam - 1.0) * U[F_E][q];", "qp[m] = gam * U[F_E][q];"),
     ("euler_h", "g->acc[a][q] = (Pi[j] - Pi[j - 1]) / h;", "g->acc[a][q] = (Pi[j] - Pi[j - 1]);"),
+    ("inflow_side", "const double *st = g->inflow[2 * a + (i >= G + n ? 1 : 0)];",
+     "const double *st = g->inflow[2 * a + (i >= G + n ? 0 : 1)];"),
+    ("inflow_energy", "st[F_ET] = e + ke;", "st[F_ET] = e;"),
 ]
 
 RUNNER = r"""
