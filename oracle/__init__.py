@@ -6,5 +6,4 @@ product path never imports, links or executes anything here, and this
 package imports nothing from the product package.
 """
 from .oracle import (Oracle, avg_left, avg_right, build, lib_path, load_library, max_threads,  # noqa: F401
-                     set_threads,
-                     reconstruct_line)
+                     multipole_value, reconstruct_line, set_threads, sine_transform)

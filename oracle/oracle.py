@@ -82,6 +82,16 @@ def load_library(path: str | None = None) -> C.CDLL:
     lib.og_max_threads.argtypes = []
     lib.og_set_threads.restype = None
     lib.og_set_threads.argtypes = [C.c_int]
+    lib.og_set_self_gravity.restype = C.c_int
+    lib.og_set_self_gravity.argtypes = [C.c_void_p, C.c_double]
+    lib.og_multipole_moments.restype = None
+    lib.og_multipole_moments.argtypes = [C.c_void_p, dp]
+    lib.og_multipole_value.restype = C.c_double
+    lib.og_multipole_value.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_double]
+    lib.og_sine_transform.restype = None
+    lib.og_sine_transform.argtypes = [dp, C.c_long, dp]
+    lib.og_potential.restype = C.c_int
+    lib.og_potential.argtypes = [C.c_void_p, dp]
     lib.og_avg_right.restype = C.c_double
     lib.og_avg_right.argtypes = [C.c_double] * 4
     _cache[path] = lib
@@ -116,6 +126,23 @@ def reconstruct_line(q, lib: C.CDLL | None = None):
     return qL, qR, q6
 
 
+def sine_transform(x, lib: C.CDLL | None = None) -> np.ndarray:
+    """y_j = sum_k x_k sin(pi j k / (n+1)), j, k = 1..n (Sec. 2.5, stages 2-3)."""
+    lib = lib or load_library()
+    x = _f64(x)
+    y = np.empty_like(x)
+    lib.og_sine_transform(_dp(x), x.size, _dp(y))
+    return y
+
+
+def multipole_value(mom, G, x, y, z, lib: C.CDLL | None = None) -> float:
+    """Two-term multipole potential at (x, y, z) of the moments
+    mom = (M, Ix, Iy, Iz, Ixy, Ixz, Iyz) (Sec. 2.5, stage 1)."""
+    lib = lib or load_library()
+    m = _f64(mom)
+    return lib.og_multipole_value(_dp(m), float(G), float(x), float(y), float(z))
+
+
 def avg_left(qL, qR, q6, z, lib: C.CDLL | None = None) -> float:
     return (lib or load_library()).og_avg_left(qL, qR, q6, z)
 
@@ -131,11 +158,14 @@ class Oracle:
     ``bc`` a boundary name or a per-axis list of (lo, hi) names;
     ``potential`` None, ("log", v0, rc, q, cx, cy, cz) or ("uniform", gx, gy, gz);
     ``inflow`` maps a face (2 * axis + side, side 0 low / 1 high) with an
-    "inflow" boundary to its ghost state (rho, vx, vy, vz, p).
+    "inflow" boundary to its ghost state (rho, vx, vy, vz, p);
+    ``self_gravity`` = G > 0 adds the force of the potential of the gas's own
+    mass (Sec. 2.5; 3-D, cubic cells).
     """
 
     def __init__(self, ndim, n, lo, hi, gamma, cfl, bc="periodic", vacuum_ratio=1e-5,
-                 potential=None, first_order=False, lib: C.CDLL | str | None = None, inflow=None):
+                 potential=None, first_order=False, lib: C.CDLL | str | None = None, inflow=None,
+                 self_gravity=None):
         self.lib = lib if isinstance(lib, C.CDLL) else load_library(lib)
         self.ndim = int(ndim)
         n = list(n) + [1] * (3 - len(n))
@@ -165,6 +195,9 @@ class Oracle:
             raise ValueError("og_create failed")
         for face, st in (inflow or {}).items():
             self.lib.og_set_inflow(self.g, int(face), *[float(v) for v in st])
+        if self_gravity is not None:
+            if self.lib.og_set_self_gravity(self.g, float(self_gravity)) != 0:
+                raise ValueError("self-gravity needs a 3-D grid of cubic cells")
 
     def __del__(self):
         g = getattr(self, "g", None)
@@ -242,6 +275,21 @@ class Oracle:
     @property
     def last_max_z_lagr(self) -> float:
         return self.lib.og_last_max_z_lagr(self.g)
+
+    def potential(self) -> np.ndarray:
+        """Self-gravity potential of the current state on the interior cells
+        and the one-cell shell around them: shape (nz+2, ny+2, nx+2)."""
+        nx, ny, nz = self.n
+        out = np.empty((nz + 2, ny + 2, nx + 2))
+        if self.lib.og_potential(self.g, _dp(out)) != 0:
+            raise ValueError("self-gravity is off")
+        return out
+
+    def moments(self) -> np.ndarray:
+        """(M, Ix, Iy, Iz, Ixy, Ixz, Iyz) of the cell masses (Sec. 2.5, stage 1)."""
+        out = np.zeros(7)
+        self.lib.og_multipole_moments(self.g, _dp(out))
+        return out
 
     def primitive(self):
         r = self.get("rho")

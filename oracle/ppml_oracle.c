@@ -41,6 +41,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
 #define NF 6
 enum { F_RHO = 0, F_MX = 1, F_MY = 2, F_MZ = 3, F_ET = 4, F_E = 5 };
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2, BC_INFLOW = 3 };
@@ -66,6 +70,9 @@ typedef struct {
     double *W[NF];   /* Eulerian-stage output U^{n+1/2}, ghosted           */
     double *acc[NF]; /* per-cell sums of directional differences           */
     double last_max_z_euler, last_max_z_lagr;
+    int self_grav;   /* 1: the self-gravity potential enters the force      */
+    double grav_G;   /* gravitational constant of Delta Phi = 4 pi G rho    */
+    double *phi;     /* potential on the interior plus a one-cell shell     */
 } og_grid;
 
 static long ncell_ghosted(const og_grid *g) { return g->N[0] * g->N[1] * g->N[2]; }
@@ -249,6 +256,7 @@ void og_destroy(og_grid *g)
         free(g->W[f]);
         free(g->acc[f]);
     }
+    free(g->phi);
     free(g);
 }
 
@@ -408,6 +416,204 @@ static void potential_grad(const og_grid *g, long i, long j, long k, double *gr)
     } else {
         gr[0] = gr[1] = gr[2] = 0.0;
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Self-gravity (Sec. 2.5, the Poisson solver).                             */
+/* The potential solves the 27-point finite-difference form of             */
+/* Delta Phi = 4 pi G rho (weights -38/9 at the centre, 4/9 on the 6 face   */
+/* neighbours, 1/9 on the 12 edge neighbours, 1/36 on the 8 corners;       */
+/* right-hand side 4 pi G h^2 rho) on the interior cells.  Stage 1: the    */
+/* cells of the one-cell shell around the box take the two-term multipole  */
+/* expansion of the mass about the coordinate origin, and every shell      */
+/* value the stencil of an interior cell touches moves to the right-hand   */
+/* side.  Stages 2-3: the Dirichlet problem is diagonal in the sine basis  */
+/* sin(pi j k / (N+1)) of each axis (the Fourier basis of the odd          */
+/* extension, period 2(N+1)); the amplitudes are divided by the stencil's  */
+/* eigenvalue and transformed back.  Cells must be cubes; 3-D only.        */
+/* Readings: the multipole is taken about the coordinate origin; its       */
+/* quadrupole term carries the factor 1/2 of MacCullagh's formula; the     */
+/* eigenvalue is -6 (1 - prod_a (1 - (2/3) sin^2(pi j_a / (2 (N_a+1)))))   */
+/* (negative: the potential of a positive mass is negative); the force     */
+/* uses the central difference of Phi across each cell.                    */
+/* ------------------------------------------------------------------------ */
+static long pidx(const og_grid *g, long i, long j, long k)
+{
+    return ((k + 1) * (g->n[1] + 2) + (j + 1)) * (g->n[0] + 2) + (i + 1);
+}
+
+/* Enable self-gravity with constant G (3-D, cubic cells).  0 or -1. */
+int og_set_self_gravity(og_grid *g, double G)
+{
+    if (g->ndim != 3) return -1;
+    double h = g->h[0];
+    if (fabs(g->h[1] - h) > 1e-12 * h || fabs(g->h[2] - h) > 1e-12 * h) return -1;
+    if (!g->phi) g->phi = (double *)calloc((size_t)((g->n[0] + 2) * (g->n[1] + 2) * (g->n[2] + 2)), sizeof(double));
+    g->self_grav = 1;
+    g->grav_G = G;
+    return 0;
+}
+
+/* Mass and second moments of the cell masses m = rho h^3 (cell centres,
+ * coordinate origin): mom = {M, Ix, Iy, Iz, Ixy, Ixz, Iyz} with
+ * Ix = sum (y^2 + z^2) m, Iy = sum (x^2 + z^2) m, Iz = sum (x^2 + y^2) m,
+ * Ixy = sum x y m, Ixz = sum x z m, Iyz = sum y z m (stage 1). */
+void og_multipole_moments(const og_grid *g, double *mom)
+{
+    double vol = g->h[0] * g->h[1] * g->h[2];
+    for (int q = 0; q < 7; q++) mom[q] = 0.0;
+    for (long k = 0; k < g->n[2]; k++)
+        for (long j = 0; j < g->n[1]; j++)
+            for (long i = 0; i < g->n[0]; i++) {
+                double x = g->lo[0] + ((double)i + 0.5) * g->h[0];
+                double y = g->lo[1] + ((double)j + 0.5) * g->h[1];
+                double z = g->lo[2] + ((double)k + 0.5) * g->h[2];
+                double m = g->U[F_RHO][gidx(g, i + g->g[0], j + g->g[1], k + g->g[2])] * vol;
+                mom[0] += m;
+                mom[1] += (y * y + z * z) * m;
+                mom[2] += (x * x + z * z) * m;
+                mom[3] += (x * x + y * y) * m;
+                mom[4] += x * y * m;
+                mom[5] += x * z * m;
+                mom[6] += y * z * m;
+            }
+}
+
+/* Two-term multipole potential at (x, y, z) (stage 1):
+ * -G M / r - G (Ix + Iy + Iz - 3 I0) / (2 r^3), where I0 is the moment of
+ * inertia about the line from the origin through the point. */
+double og_multipole_value(const double *mom, double G, double x, double y, double z)
+{
+    double r2 = x * x + y * y + z * z;
+    double r = sqrt(r2);
+    double I0 = ((x * x * mom[1] + y * y * mom[2] + z * z * mom[3]) -
+                 2.0 * (x * y * mom[4] + x * z * mom[5] + y * z * mom[6])) / r2;
+    return -G * mom[0] / r - G * (mom[1] + mom[2] + mom[3] - 3.0 * I0) / (2.0 * r2 * r);
+}
+
+/* Sine transform of one line of n values: y_j = sum_k x_k sin(pi j k / (n+1)),
+ * j, k = 1..n (x[k-1], y[j-1]); the same sum transforms back up to the
+ * factor 2 / (n+1). */
+void og_sine_transform(const double *x, long n, double *y)
+{
+    for (long j = 1; j <= n; j++) {
+        double s = 0.0;
+        for (long k = 1; k <= n; k++) s += x[k - 1] * sin(M_PI * (double)(j * k) / (double)(n + 1));
+        y[j - 1] = s;
+    }
+}
+
+/* Sine transform of every line of axis a of the interior array A (C order
+ * [k][j][i], extents n[0..2]) into B. */
+static void transform_axis(const og_grid *g, int a, const double *A, double *B)
+{
+    long n0 = g->n[0], n1 = g->n[1], n2 = g->n[2];
+    long n = g->n[a];
+    long s = a == 0 ? 1 : (a == 1 ? n0 : n0 * n1);
+    long nl = n0 * n1 * n2 / n;
+    /* sine table of this axis (the definition above, tabulated) */
+    double *S = (double *)malloc((size_t)(n * n) * sizeof(double));
+    for (long j = 1; j <= n; j++)
+        for (long k = 1; k <= n; k++) S[(j - 1) * n + (k - 1)] = sin(M_PI * (double)(j * k) / (double)(n + 1));
+#pragma omp parallel for schedule(static)
+    for (long l = 0; l < nl; l++) {
+        long base;
+        if (a == 0) base = l * n0;
+        else if (a == 1) base = (l / n0) * n0 * n1 + (l % n0);
+        else base = l;
+        for (long j = 0; j < n; j++) {
+            double acc = 0.0;
+            for (long k = 0; k < n; k++) acc += A[base + k * s] * S[j * n + k];
+            B[base + j * s] = acc;
+        }
+    }
+    free(S);
+}
+
+static double stencil_weight(int nd) { return nd == 1 ? 4.0 / 9.0 : (nd == 2 ? 1.0 / 9.0 : 1.0 / 36.0); }
+
+/* Potential of the current density on the interior and the shell. */
+static void poisson(og_grid *g)
+{
+    long n0 = g->n[0], n1 = g->n[1], n2 = g->n[2];
+    double h = g->h[0], G = g->grav_G;
+    double mom[7];
+    og_multipole_moments(g, mom);
+    /* stage 1: shell values */
+    for (long k = -1; k <= n2; k++)
+        for (long j = -1; j <= n1; j++)
+            for (long i = -1; i <= n0; i++) {
+                if (i >= 0 && i < n0 && j >= 0 && j < n1 && k >= 0 && k < n2) continue;
+                double x = g->lo[0] + ((double)i + 0.5) * h;
+                double y = g->lo[1] + ((double)j + 0.5) * h;
+                double z = g->lo[2] + ((double)k + 0.5) * h;
+                g->phi[pidx(g, i, j, k)] = og_multipole_value(mom, G, x, y, z);
+            }
+    /* right-hand side: 4 pi G h^2 rho minus the stencil's shell terms */
+    long nc = n0 * n1 * n2;
+    double *A = (double *)malloc((size_t)nc * sizeof(double));
+    double *B = (double *)malloc((size_t)nc * sizeof(double));
+    for (long k = 0; k < n2; k++)
+        for (long j = 0; j < n1; j++)
+            for (long i = 0; i < n0; i++) {
+                double b = 4.0 * M_PI * G * h * h * g->U[F_RHO][gidx(g, i + g->g[0], j + g->g[1], k + g->g[2])];
+                for (int dz = -1; dz <= 1; dz++)
+                    for (int dy = -1; dy <= 1; dy++)
+                        for (int dx = -1; dx <= 1; dx++) {
+                            long ii = i + dx, jj = j + dy, kk = k + dz;
+                            if (ii >= 0 && ii < n0 && jj >= 0 && jj < n1 && kk >= 0 && kk < n2) continue;
+                            int nd = abs(dx) + abs(dy) + abs(dz);
+                            b -= stencil_weight(nd) * g->phi[pidx(g, ii, jj, kk)];
+                        }
+                A[(k * n1 + j) * n0 + i] = b;
+            }
+    /* stage 2: forward transform */
+    transform_axis(g, 0, A, B);
+    transform_axis(g, 1, B, A);
+    transform_axis(g, 2, A, B);
+    /* stage 3: divide by the eigenvalue (and the inverse transform's factors) */
+    double norm = (2.0 / (double)(n0 + 1)) * (2.0 / (double)(n1 + 1)) * (2.0 / (double)(n2 + 1));
+    for (long k = 0; k < n2; k++)
+        for (long j = 0; j < n1; j++)
+            for (long i = 0; i < n0; i++) {
+                double sx = sin(M_PI * (double)(i + 1) / (2.0 * (double)(n0 + 1)));
+                double sy = sin(M_PI * (double)(j + 1) / (2.0 * (double)(n1 + 1)));
+                double sz = sin(M_PI * (double)(k + 1) / (2.0 * (double)(n2 + 1)));
+                double prod = (1.0 - 2.0 * sx * sx / 3.0) * (1.0 - 2.0 * sy * sy / 3.0) * (1.0 - 2.0 * sz * sz / 3.0);
+                double lam = -6.0 * (1.0 - prod);
+                B[(k * n1 + j) * n0 + i] = B[(k * n1 + j) * n0 + i] / lam * norm;
+            }
+    /* back to physical space */
+    transform_axis(g, 0, B, A);
+    transform_axis(g, 1, A, B);
+    transform_axis(g, 2, B, A);
+    for (long k = 0; k < n2; k++)
+        for (long j = 0; j < n1; j++)
+            for (long i = 0; i < n0; i++) g->phi[pidx(g, i, j, k)] = A[(k * n1 + j) * n0 + i];
+    free(A);
+    free(B);
+}
+
+/* Solve for the potential of the current state and copy it out with its
+ * shell: (n0+2)(n1+2)(n2+2) values, C order, shell included.  -1 if
+ * self-gravity is off. */
+int og_potential(og_grid *g, double *out)
+{
+    if (!g->self_grav) return -1;
+    poisson(g);
+    long np = (g->n[0] + 2) * (g->n[1] + 2) * (g->n[2] + 2);
+    memcpy(out, g->phi, (size_t)np * sizeof(double));
+    return 0;
+}
+
+/* Gradient of the self-gravity potential at interior cell (i, j, k): central
+ * differences across the cell. */
+static void self_gravity_grad(const og_grid *g, long i, long j, long k, double *gr)
+{
+    double h2 = 2.0 * g->h[0];
+    gr[0] = (g->phi[pidx(g, i + 1, j, k)] - g->phi[pidx(g, i - 1, j, k)]) / h2;
+    gr[1] = (g->phi[pidx(g, i, j + 1, k)] - g->phi[pidx(g, i, j - 1, k)]) / h2;
+    gr[2] = (g->phi[pidx(g, i, j, k + 1)] - g->phi[pidx(g, i, j, k - 1)]) / h2;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -573,9 +779,14 @@ static void eulerian_stage(og_grid *g, double tau)
                 }
                 g->W[F_ET][q] = U[F_ET][q] - tau * g->acc[3][q];
                 g->W[F_E][q] = U[F_E][q] - ((tau * (gam - 1.0)) * U[F_E][q]) * g->acc[4][q];
-                if (g->potential != POT_NONE) {
+                if (g->potential != POT_NONE || g->self_grav) {
                     double gr[3];
                     potential_grad(g, i, j, k, gr);
+                    if (g->self_grav) {
+                        double gs[3];
+                        self_gravity_grad(g, i, j, k, gs);
+                        for (int a = 0; a < 3; a++) gr[a] += gs[a];
+                    }
                     /* force along the active axes only */
                     for (int a = g->ndim; a < 3; a++) gr[a] = 0.0;
                     double work = U[F_MX][q] * gr[0] + U[F_MY][q] * gr[1] + U[F_MZ][q] * gr[2];
@@ -712,6 +923,7 @@ static void energy_correction(og_grid *g)
 /* One full step U^n -> U^{n+1} with time step tau. */
 void og_step(og_grid *g, double tau)
 {
+    if (g->self_grav) poisson(g);
     fill_ghosts(g, g->U);
     eulerian_stage(g, tau);
     fill_ghosts(g, g->W);

@@ -49,6 +49,7 @@ class Problem:
     nsteps: int | None = None
     t_stop: float | None = None
     inflow: dict | None = None       # face (2 * axis + side) -> ghost state (rho, vx, vy, vz, p)
+    self_gravity: float | None = None  # G of the self-gravity potential (Sec. 2.5), or None
 
     @property
     def shape(self):
@@ -258,6 +259,33 @@ def disk(nx: int = 512, ny: int = 512, nz: int = 64, seed: int = 0, v0: float = 
     return Problem(f"disk_{nx}x{ny}x{nz}_s{seed}", 3, n3, lo, hi, gamma, cfl, bc,
                    np.ascontiguousarray(rho), np.ascontiguousarray(vx), np.ascontiguousarray(vy), vz,
                    np.ascontiguousarray(p), pot, nsteps, None)
+
+
+def gravity_sphere(n: int | tuple = 32, L: float = 2.0, G: float = 1.0, rho_floor: float = 1e-3,
+                   p0: float = 0.05, gamma: float = 5.0 / 3.0, cfl: float = 0.3, seed: int | None = None,
+                   noise: float = 0.0) -> Problem:
+    """The density of the Poisson verification problem (Sec. 2.5; 2r^3 - 3r^2 + 1
+    inside r = 1, the reading under which the printed potential solves it) as
+    a self-gravitating gas ball at rest on [-L, L]^3 (cubic cells), over a
+    uniform floor density, at uniform pressure p0 (so it starts to collapse);
+    outflow boundaries.  noise > 0 multiplies the density by a seeded
+    lognormal factor."""
+    n3 = (n, n, n) if isinstance(n, int) else tuple(n)
+    h = 2.0 * L / n3[0]
+    lo = tuple(-0.5 * n3[a] * h for a in range(3))
+    hi = tuple(0.5 * n3[a] * h for a in range(3))
+    X, Y, Z = _mesh(n3, lo, hi)
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    rho = np.where(r <= 1.0, 2.0 * r ** 3 - 3.0 * r ** 2 + 1.0, 0.0) + rho_floor
+    if noise > 0.0:
+        rho = rho * np.exp(noise * np.random.default_rng(seed).standard_normal(rho.shape))
+    z = np.zeros(X.shape)
+    p = np.full(X.shape, p0)
+    nm = "x".join(str(v) for v in n3)
+    prob = Problem(f"gravity_sphere_{nm}", 3, n3, lo, hi, gamma, cfl, [("outflow", "outflow")] * 3,
+                   np.ascontiguousarray(rho), z, z.copy(), z.copy(), p)
+    prob.self_gravity = G
+    return prob
 
 
 def aksenov(n: int, cfl: float = 0.2) -> Problem:

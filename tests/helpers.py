@@ -14,7 +14,8 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 def make_oracle(prob, lib=None, first_order=False, cfl=None, vacuum_ratio=1e-5):
     o = oracle.Oracle(prob.ndim, prob.n, prob.lo, prob.hi, prob.gamma, prob.cfl if cfl is None else cfl,
                       bc=prob.bc, vacuum_ratio=vacuum_ratio, potential=prob.potential,
-                      first_order=first_order, lib=lib, inflow=getattr(prob, "inflow", None))
+                      first_order=first_order, lib=lib, inflow=getattr(prob, "inflow", None),
+                      self_gravity=getattr(prob, "self_gravity", None))
     o.set_primitive(prob.rho, prob.vx, prob.vy, prob.vz, prob.p)
     return o
 

@@ -72,6 +72,21 @@ MUTANTS = [
     ("inflow_side", "const double *st = g->inflow[2 * a + (i >= G + n ? 1 : 0)];",
      "const double *st = g->inflow[2 * a + (i >= G + n ? 0 : 1)];"),
     ("inflow_energy", "st[F_ET] = e + ke;", "st[F_ET] = e;"),
+    ("multipole_no_half", "/ (2.0 * r2 * r);", "/ (r2 * r);"),
+    ("multipole_cross_sign", "2.0 * (x * y * mom[4] + x * z * mom[5] + y * z * mom[6])",
+     "2.0 * (x * y * mom[4] - x * z * mom[5] + y * z * mom[6])"),
+    ("moment_Iy_axes", "mom[2] += (x * x + z * z) * m;", "mom[2] += (x * x + y * y) * m;"),
+    ("poisson_eigen_sign", "double lam = -6.0 * (1.0 - prod);", "double lam = 6.0 * (1.0 - prod);"),
+    ("poisson_eigen_period", "double sy = sin(M_PI * (double)(j + 1) / (2.0 * (double)(n1 + 1)));",
+     "double sy = sin(M_PI * (double)(j + 1) / (2.0 * (double)(n1)));"),
+    ("poisson_norm_axis", "* (2.0 / (double)(n1 + 1)) *", "* (2.0 / (double)(n0 + 1)) *"),
+    ("stencil_edge_weight", "(nd == 2 ? 1.0 / 9.0 : 1.0 / 36.0)", "(nd == 2 ? 1.0 / 36.0 : 1.0 / 9.0)"),
+    ("sine_table_period", "S[(j - 1) * n + (k - 1)] = sin(M_PI * (double)(j * k) / (double)(n + 1));",
+     "S[(j - 1) * n + (k - 1)] = sin(M_PI * (double)(j * k) / (double)(n));"),
+    ("poisson_rhs_h", "4.0 * M_PI * G * h * h *", "4.0 * M_PI * G * h *"),
+    ("gravity_gradient_h", "double h2 = 2.0 * g->h[0];", "double h2 = g->h[0];"),
+    ("gravity_gradient_axis", "gr[1] = (g->phi[pidx(g, i, j + 1, k)] - g->phi[pidx(g, i, j - 1, k)]) / h2;",
+     "gr[1] = (g->phi[pidx(g, i + 1, j, k)] - g->phi[pidx(g, i - 1, j, k)]) / h2;"),
 ]
 
 RUNNER = r"""
