@@ -292,6 +292,77 @@ def run_suite():
     return out
 
 
+# the relative errors of the Poisson solver that the paper prints (Sec. 2.5
+# table, its own machine and code), quoted beside ours as context
+PAPER_POISSON_ERR = {16: 4.799777e-05, 32: 2.978253e-06, 64: 1.862059e-07, 128: 1.164110e-08, 256: 7.278760e-10}
+
+
+def run_gravity(n=256, steps=50):
+    """Self-gravity (Sec. 2.5): the verification sphere's density as a
+    collapsing gas ball, n^3 on [-2, 2]^3, outflow, CFL 0.3; FP32 and FP64,
+    each with its own CFL steps: zone-updates/s of the whole step (potential
+    solve + both stage kernels), the split per part, the transforms'
+    algorithmic GEMM rate against the matrix-core peak, FP32 against FP64 in
+    L1 after the run; and the Poisson verification table (the analytic
+    potential's relative error on 16^3 ... 256^3, FP64)."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_1607_01105_amd import workloads as W
+    from paper_1607_01105_amd.ppml import Grid
+
+    prob = W.gravity_sphere(n, noise=0.01, seed=0)
+    cells = prob.cells
+    # sine transforms: 3 axes forward + 3 back, each 2 n_a FLOP per cell
+    gemm_flop = 4.0 * cells * sum(prob.n)
+    out = {"workload": f"self-gravitating ball {n}^3 on [-2,2]^3 (density 2r^3-3r^2+1 + 1e-3 floor, 1% noise), "
+                       f"p = 0.05, outflow, CFL 0.3, {steps} steps", "cells": cells, "steps": steps}
+    rho = {}
+    for prec in ("fp32", "fp64"):
+        g = Grid.from_problem(prob, prec=prec)
+        g.step(2)
+        g.sync()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(g.stream)
+        g.step(steps)
+        t1.record(g.stream)
+        g.sync()
+        ms = t0.elapsed_time(t1)
+        rho[prec] = g.get("rho")
+        g.set_timing(10)
+        g.step(10)
+        mg, me, ml, k = g.get_timing_split()
+        peak = 157.3 if prec == "fp32" else 78.6
+        out[prec] = {"zone_updates_per_s": cells * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+                     "split_ms": {"gravity": mg / k, "euler": me / k, "lagr": ml / k},
+                     "transforms": {"algorithmic_gemm_flop": gemm_flop, "achieved_TFLOPs_over_gravity_solve":
+                                    gemm_flop / (mg / k * 1e-3) / 1e12, "mfma_peak_TFLOPs": peak}}
+        _log(f"[bench] gravity {n}^3 {prec}: {out[prec]['ms_per_step']:.3f} ms/step, solve {mg / k:.3f} ms")
+        del g
+        torch.cuda.empty_cache()
+    out["l1_rho_fp32_vs_fp64_own_steps"] = float(np.sum(np.abs(rho["fp32"] - rho["fp64"])) / np.sum(rho["fp64"]))
+    table = {}
+    for m in (16, 32, 64, 128, 256):
+        sp = W.gravity_sphere(m, rho_floor=1e-12)
+        g = Grid.from_problem(sp, prec="fp64")
+        phi = g.potential()[1:-1, 1:-1, 1:-1]
+        del g
+        X, Y, Z = (sp.centres(a) for a in range(3))
+        Zm, Ym, Xm = np.meshgrid(Z, Y, X, indexing="ij")
+        r = np.sqrt(Xm ** 2 + Ym ** 2 + Zm ** 2)
+        pi = math.pi
+        ex = np.where(r <= 1.0, 4 * pi / 15 * r ** 5 - 3 * pi / 5 * r ** 4 + 2 * pi / 3 * r ** 2 - 3 * pi / 5,
+                      -4 * pi / (15 * r))
+        table[str(m)] = {"rel_err": float(np.max(np.abs(phi - ex)) / np.max(np.abs(ex))),
+                         "paper_printed": PAPER_POISSON_ERR[m]}
+    torch.cuda.empty_cache()
+    out["poisson_sphere_table_fp64"] = table
+    return out
+
+
 def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -455,6 +526,8 @@ def main():
         out["riemann_1d"] = run_riemann_1d()
         print("[bench] test-suite workloads", file=sys.stderr, flush=True)
         out["suite"] = run_suite()
+        print("[bench] self-gravity workload", file=sys.stderr, flush=True)
+        out["gravity"] = run_gravity()
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob)

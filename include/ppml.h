@@ -92,11 +92,30 @@ typedef struct {
     int32_t tile;          /* work-group tile shape of the stage kernels: index in
                               the list of ppml_tile_shape (0 = default); changes
                               the speed only, never the results                  */
-    int32_t reserved;      /* must be 0                                             */
+    int32_t self_gravity;  /* 1: add the force of the gas's own potential (Sec. 2.5,
+                              see below); 0: none.  Needs ndim = 3 and cubic cells */
     double inflow[6][5];   /* ghost state (rho, vx, vy, vz, p) of face 2*axis+side
                               (side 0 low, 1 high) where that face is PPML_INFLOW;
                               rho, p > 0; converted like ppml_set_primitive   */
+    double grav_G;         /* gravitational constant G of Delta Phi = 4 pi G rho
+                              (used when self_gravity = 1; > 0)                  */
 } ppml_desc;
+
+/* Self-gravity (Sec. 2.5, the Poisson solver).  Before each step's Eulerian
+ * stage the potential of the current density is found from the 27-point
+ * finite-difference Poisson equation (weights -38/9, 4/9, 1/9, 1/36;
+ * right-hand side 4 pi G h^2 rho) on the interior cells, with the values of
+ * a one-cell shell around the box taken from the two-term multipole
+ * expansion about the coordinate origin (monopole and quadrupole; the
+ * quadrupole with MacCullagh's factor 1/2) and moved to the right-hand side;
+ * the Dirichlet problem is solved exactly by sine transforms along each axis
+ * (products with the N x N sine matrices on the matrix cores), division by
+ * the stencil's eigenvalues and the inverse transforms.  The force terms of
+ * eqs. (2)-(3) then use the central difference of the potential across each
+ * cell, added to any fixed potential's gradient.  The scratch area grows by
+ * the potential, two work arrays of the grid's size and the sine tables
+ * (see ppml_scratch_bytes).  Grids with self-gravity step alone, not in a
+ * batch. */
 
 /* Work-group tile shapes of the stage kernels for grids of ndim dimensions:
  * ppml_tile_count returns how many there are (>= 1) or PPML_EINVAL;
@@ -160,6 +179,13 @@ int ppml_max_speeds(ppml_grid *g, double *vmax, double *cmax);
  * Errors: PPML_EINVAL (field of an unused axis), PPML_ENOMEM, PPML_EHIP. */
 int ppml_get_conserved(ppml_grid *g, int32_t field, double *host_out);
 
+/* Self-gravity potential (Sec. 2.5): synchronize, solve for the potential of
+ * the current state and copy it to host_out as FP64, shell included:
+ * (n[0]+2)(n[1]+2)(n[2]+2) values, C order [k+1][j+1][i+1] (index 0 and
+ * n+1 along an axis are the shell).  Errors: PPML_EINVAL (NULL output,
+ * self-gravity off), PPML_ESTATE (state never set), PPML_ENOMEM, PPML_EHIP. */
+int ppml_get_potential(ppml_grid *g, double *host_out);
+
 /* Synchronize and return the FP64 sums over all cells of the six conserved
  * densities (unused momentum axes give 0); the summation order is fixed,
  * so repeated calls on the same state give identical bits. */
@@ -185,6 +211,11 @@ const char *ppml_last_error(void);
  * timed, and starts a new accumulation.  Errors: PPML_EINVAL, PPML_EHIP. */
 int ppml_set_timing(ppml_grid *g, int32_t cap);
 int ppml_get_timing(ppml_grid *g, double *ms_euler, double *ms_lagr, int64_t *nsteps);
+
+/* As ppml_get_timing, with the self-gravity solve of each timed step (moments,
+ * boundary values, transforms; 0 without self-gravity) split off:
+ * ms[0] = gravity, ms[1] = Eulerian kernel, ms[2] = Lagrangian kernel. */
+int ppml_get_timing_split(ppml_grid *g, double ms[3], int64_t *nsteps);
 
 /* ---- Batches: many independent grids stepped together ------------------
  * A batch steps all its grids in the same kernel launches (one Eulerian and

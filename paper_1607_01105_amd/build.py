@@ -39,7 +39,8 @@ def build_one(out: str, exact: bool) -> str:
         # subnormals
         flags += ["-fno-hip-fp32-correctly-rounded-divide-sqrt", "-fgpu-flush-denormals-to-zero"]
     tmp = out + ".tmp"
-    cmd = [HIPCC, *flags, SRC, "-o", tmp]
+    # rocBLAS runs the GEMMs of the self-gravity sine transforms
+    cmd = [HIPCC, *flags, SRC, "-o", tmp, "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

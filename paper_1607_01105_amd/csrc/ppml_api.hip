@@ -3,6 +3,7 @@
 // ppml_kernels.hip on the caller's stream.  No computation of the method
 // happens on the host.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <cmath>
 #include <cstddef>
@@ -13,6 +14,7 @@
 #include <vector>
 
 #include "../../include/ppml.h"
+#include "ppml_gravity.hpp"
 #include "ppml_kernels.hpp"
 
 using namespace ppml;
@@ -119,7 +121,16 @@ int validate(const ppml_desc *d)
     if (d->flags & ~PPML_FLAG_FIRST_ORDER) return fail(PPML_EINVAL, "unknown flags 0x%x", d->flags);
     if (d->tile < 0 || d->tile >= NTILE[d->ndim])
         return fail(PPML_EINVAL, "tile %d out of range [0, %d) for ndim %d", d->tile, NTILE[d->ndim], d->ndim);
-    if (d->reserved != 0) return fail(PPML_EINVAL, "reserved descriptor field must be 0");
+    if (d->self_gravity != 0 && d->self_gravity != 1) return fail(PPML_EINVAL, "self_gravity must be 0 or 1");
+    if (d->self_gravity) {
+        if (d->ndim != 3) return fail(PPML_EINVAL, "self-gravity needs ndim = 3");
+        const double h0 = (d->hi[0] - d->lo[0]) / (double)d->n[0];
+        for (int a = 1; a < 3; a++) {
+            const double ha = (d->hi[a] - d->lo[a]) / (double)d->n[a];
+            if (std::fabs(ha - h0) > 1e-12 * h0) return fail(PPML_EINVAL, "self-gravity needs cubic cells");
+        }
+        if (!(d->grav_G > 0.0) || !std::isfinite(d->grav_G)) return fail(PPML_EINVAL, "grav_G must be > 0");
+    }
     return PPML_OK;
 }
 
@@ -130,8 +141,15 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 int totals_blocks(long long n) { return (int)std::min<long long>(1024, (n + 4095) / 4096 > 0 ? (n + 4095) / 4096 : 1); }
 
 struct ScratchLayout {
-    size_t half, ctrl, partial, totals, total;
+    size_t half, ctrl, partial, totals;
+    // self-gravity: padded potential, two work arrays, sine matrices,
+    // eigenvalue factors, moment partials
+    size_t phi, wx, wy, sx, sy, sz, fx, fy, fz, gpart;
+    size_t total;
 };
+
+// Moment reduction of the self-gravity solve: fixed block count (fixed order).
+int grav_blocks(long long n) { return (int)std::min<long long>(1024, (n + 2047) / 2048 > 0 ? (n + 2047) / 2048 : 1); }
 
 ScratchLayout layout(const ppml_desc *d)
 {
@@ -144,6 +162,31 @@ ScratchLayout layout(const ppml_desc *d)
     sz += align_up((size_t)totals_blocks(ncells(d)) * 6 * sizeof(double));
     L.totals = sz;
     sz += align_up(8 * sizeof(double));
+    L.phi = L.wx = L.wy = L.sx = L.sy = L.sz = L.fx = L.fy = L.fz = L.gpart = 0;
+    if (d->self_gravity) {
+        const size_t e = elem(d);
+        const size_t n0 = (size_t)d->n[0], n1 = (size_t)d->n[1], n2 = (size_t)d->n[2];
+        L.phi = sz;
+        sz += align_up((n0 + 2) * (n1 + 2) * (n2 + 2) * e);
+        L.wx = sz;
+        sz += align_up(n0 * n1 * n2 * e);
+        L.wy = sz;
+        sz += align_up(n0 * n1 * n2 * e);
+        L.sx = sz;
+        sz += align_up(n0 * n0 * e);
+        L.sy = sz;
+        sz += align_up(n1 * n1 * e);
+        L.sz = sz;
+        sz += align_up(n2 * n2 * e);
+        L.fx = sz;
+        sz += align_up(n0 * sizeof(double));
+        L.fy = sz;
+        sz += align_up(n1 * sizeof(double));
+        L.fz = sz;
+        sz += align_up(n2 * sizeof(double));
+        L.gpart = sz;
+        sz += align_up((size_t)grav_blocks(ncells(d)) * GRAV_MOM * sizeof(double));
+    }
     L.total = sz;
     return L;
 }
@@ -163,8 +206,14 @@ struct ppml_grid {
     double *totals;
     bool in_batch;         // admitted to a batch: stepped only by the batch
     bool has_state;
-    std::vector<hipEvent_t> ev;  // 3 events per timed step
+    std::vector<hipEvent_t> ev;  // 4 events per timed step
     long long timed;             // steps recorded since the last read
+    // self-gravity (Sec. 2.5)
+    rocblas_handle blas;
+    void *phi, *wx, *wy, *sx, *sy, *sz;
+    double *fx, *fy, *fz, *gpart;
+    double grav_coef;      // 4 pi G h^2
+    double grav_norm;      // prod_a 2 / (n_a + 1)
 };
 
 namespace {
@@ -191,22 +240,114 @@ template <typename T, int NDIM> void launch_stages(ppml_grid *g, hipEvent_t *ev)
         const GridParams &gl = g->gpL;
         const int nbe = ge.tiles[0] * ge.tiles[1] * ge.tiles[2];
         const int nbl = gl.tiles[0] * gl.tiles[1] * gl.tiles[2];
-        if (ev) (void)hipEventRecord(ev[0], g->stream);
-        k_euler<T, NDIM, TL::tx, TL::ty><<<nbe, TL::nt, 0, g->stream>>>(U, W, ge, g->ctrl);
         if (ev) (void)hipEventRecord(ev[1], g->stream);
-        k_lagr<T, NDIM, TL::tx, TL::ty, LG<T>::g><<<nbl, TL::nt, 0, g->stream>>>(W, Us, gl, g->ctrl);
+        if constexpr (NDIM == 3) {
+            if (ge.self_grav)
+                k_euler<T, 3, TL::tx, TL::ty, true><<<nbe, TL::nt, 0, g->stream>>>(U, W, ge, g->ctrl);
+            else
+                k_euler<T, 3, TL::tx, TL::ty><<<nbe, TL::nt, 0, g->stream>>>(U, W, ge, g->ctrl);
+        } else {
+            k_euler<T, NDIM, TL::tx, TL::ty><<<nbe, TL::nt, 0, g->stream>>>(U, W, ge, g->ctrl);
+        }
         if (ev) (void)hipEventRecord(ev[2], g->stream);
+        k_lagr<T, NDIM, TL::tx, TL::ty, LG<T>::g><<<nbl, TL::nt, 0, g->stream>>>(W, Us, gl, g->ctrl);
+        if (ev) (void)hipEventRecord(ev[3], g->stream);
     });
 }
 
-template <typename T> void launch_step(ppml_grid *g, hipEvent_t *ev)
+// GEMMs of the sine transforms (column-major view of the C-order arrays:
+// a matrix with leading dimension n0 has the x index as its row).
+rocblas_status gemm(rocblas_handle h, int m, int n, int k, const float *A, int lda, long long sa, const float *B,
+                    int ldb, long long sb, float *C, int ldc, long long sc, int batch)
 {
-    // ev (may be NULL): events recorded before, between and after the kernels
+    const float one = 1.0f, zero = 0.0f;
+    if (batch == 1)
+        return rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_none, m, n, k, &one, A, lda, B, ldb, &zero,
+                             C, ldc);
+    return rocblas_sgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, m, n, k, &one, A, lda, sa,
+                                         B, ldb, sb, &zero, C, ldc, sc, batch);
+}
+
+rocblas_status gemm(rocblas_handle h, int m, int n, int k, const double *A, int lda, long long sa, const double *B,
+                    int ldb, long long sb, double *C, int ldc, long long sc, int batch)
+{
+    const double one = 1.0, zero = 0.0;
+    if (batch == 1)
+        return rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, m, n, k, &one, A, lda, B, ldb, &zero,
+                             C, ldc);
+    return rocblas_dgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, m, n, k, &one, A, lda, sa,
+                                         B, ldb, sb, &zero, C, ldc, sc, batch);
+}
+
+// Sine transform of every line of one axis: x (C = Sx A over the n1 n2
+// columns), y (per plane: C_k = A_k Sy), z (C = A Sz over the n0 n1 rows).
+// Sine matrices are symmetric.
+template <typename T> int sine_transform(ppml_grid *g, int axis, const T *A, T *C)
+{
+    const int n0 = g->gp.n[0], n1 = g->gp.n[1], n2 = g->gp.n[2];
+    rocblas_status st;
+    if (axis == 0)
+        st = gemm(g->blas, n0, n1 * n2, n0, (const T *)g->sx, n0, 0, A, n0, 0, C, n0, 0, 1);
+    else if (axis == 1)
+        st = gemm(g->blas, n0, n1, n1, A, n0, (long long)n0 * n1, (const T *)g->sy, n1, 0, C, n0, (long long)n0 * n1,
+                  n2);
+    else
+        st = gemm(g->blas, n0 * n1, n2, n2, A, n0 * n1, 0, (const T *)g->sz, n2, 0, C, n0 * n1, 0, 1);
+    if (st != rocblas_status_success) return fail(PPML_EHIP, "rocBLAS GEMM of the sine transform: status %d", (int)st);
+    return PPML_OK;
+}
+
+// The self-gravity potential of the current state into g->phi (Sec. 2.5).
+template <typename T> int launch_gravity(ppml_grid *g)
+{
+    const GridParams &gp = g->gp;
+    const long long N = gp.ncell;
+    const int n0 = gp.n[0], n1 = gp.n[1], n2 = gp.n[2];
+    const T *rho = (const T *)g->state;
+    T *phi = (T *)g->phi;
+    T *X = (T *)g->wx;
+    T *Y = (T *)g->wy;
+    const int nb = grav_blocks(N);
+    const long long chunk = (N + nb - 1) / nb;
+    k_grav_moments_partial<T><<<nb, GRAV_THREADS, 0, g->stream>>>(rho, gp, chunk, g->gpart);
+    k_grav_moments_final<<<1, GRAV_THREADS, 0, g->stream>>>(g->gpart, nb, g->ctrl);
+    const long long nshell = (long long)(n0 + 2) * (n1 + 2) * (n2 + 2) - N;
+    k_grav_shell<T><<<(unsigned)((nshell + 255) / 256), 256, 0, g->stream>>>(gp, g->ctrl, g->d.grav_G, phi);
+    const unsigned nbc = (unsigned)((N + 255) / 256);
+    k_grav_rhs<T><<<nbc, 256, 0, g->stream>>>(rho, phi, gp, g->grav_coef, X);
+    HIPCHK(hipGetLastError());
+    int rc;
+    if ((rc = sine_transform<T>(g, 0, X, Y))) return rc;
+    if ((rc = sine_transform<T>(g, 1, Y, X))) return rc;
+    if ((rc = sine_transform<T>(g, 2, X, Y))) return rc;
+    k_grav_eigdiv<T><<<nbc, 256, 0, g->stream>>>(Y, g->fx, g->fy, g->fz, gp, g->grav_norm);
+    HIPCHK(hipGetLastError());
+    if ((rc = sine_transform<T>(g, 2, Y, X))) return rc;
+    if ((rc = sine_transform<T>(g, 1, X, Y))) return rc;
+    // inverse x transform straight into the interior of the padded potential
+    const long long pplane = (long long)(n0 + 2) * (n1 + 2);
+    T *dst = phi + pplane + (n0 + 2) + 1;
+    rocblas_status st = gemm(g->blas, n0, n1, n0, (const T *)g->sx, n0, 0, Y, n0, (long long)n0 * n1, dst, n0 + 2,
+                             pplane, n2);
+    if (st != rocblas_status_success) return fail(PPML_EHIP, "rocBLAS GEMM of the sine transform: status %d", (int)st);
+    return PPML_OK;
+}
+
+template <typename T> int launch_step(ppml_grid *g, hipEvent_t *ev)
+{
+    // ev (may be NULL): events recorded before the gravity solve, before,
+    // between and after the stage kernels
+    if (ev) (void)hipEventRecord(ev[0], g->stream);
+    if (g->gp.self_grav) {
+        int rc = launch_gravity<T>(g);
+        if (rc) return rc;
+    }
     switch (g->d.ndim) {
     case 1: launch_stages<T, 1>(g, ev); break;
     case 2: launch_stages<T, 2>(g, ev); break;
     default: launch_stages<T, 3>(g, ev); break;
     }
+    return PPML_OK;
 }
 
 template <typename T> void launch_totals(ppml_grid *g, double mean_cells)
@@ -293,14 +434,16 @@ int choose_chunks(long long tiles_xy, int nz, long long slots, double warm)
     return best;
 }
 
-template <typename T> void stage_slots(int device, int tile, long long &slots_e, long long &slots_l)
+template <typename T> void stage_slots(int device, int tile, bool sg, long long &slots_e, long long &slots_l)
 {
     int cus = 0, be = 0, bl = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 0;
     with_tile<3>(tile, [&](auto tl) {
         using TL = decltype(tl);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&be, k_euler<T, 3, TL::tx, TL::ty>, TL::nt, 0) != hipSuccess)
-            be = 0;
+        hipError_t e = sg ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&be, k_euler<T, 3, TL::tx, TL::ty, true>,
+                                                                         TL::nt, 0)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&be, k_euler<T, 3, TL::tx, TL::ty>, TL::nt, 0);
+        if (e != hipSuccess) be = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bl, k_lagr<T, 3, TL::tx, TL::ty, LG<T>::g>, TL::nt, 0) !=
             hipSuccess)
             bl = 0;
@@ -425,6 +568,51 @@ int ppml_create(const ppml_desc *d, void *state_dev, void *scratch_dev, void *hi
             return fail(PPML_EHIP, "inflow states: %s", hipGetErrorString(e));
         }
     }
+    g->blas = nullptr;
+    g->phi = g->wx = g->wy = g->sx = g->sy = g->sz = nullptr;
+    g->fx = g->fy = g->fz = g->gpart = nullptr;
+    if (d->self_gravity) {
+        g->phi = s + L.phi;
+        g->wx = s + L.wx;
+        g->wy = s + L.wy;
+        g->sx = s + L.sx;
+        g->sy = s + L.sy;
+        g->sz = s + L.sz;
+        g->fx = (double *)(s + L.fx);
+        g->fy = (double *)(s + L.fy);
+        g->fz = (double *)(s + L.fz);
+        g->gpart = (double *)(s + L.gpart);
+        gp.self_grav = 1;
+        gp.phi = g->phi;
+        const double h = gp.h[0];
+        g->grav_coef = 4.0 * M_PI * d->grav_G * h * h;
+        g->grav_norm = (2.0 / (double)(gp.n[0] + 1)) * (2.0 / (double)(gp.n[1] + 1)) * (2.0 / (double)(gp.n[2] + 1));
+        if (rocblas_create_handle(&g->blas) != rocblas_status_success) {
+            delete g;
+            return fail(PPML_EHIP, "rocblas_create_handle failed");
+        }
+        if (rocblas_set_stream(g->blas, g->stream) != rocblas_status_success) {
+            rocblas_destroy_handle(g->blas);
+            delete g;
+            return fail(PPML_EHIP, "rocblas_set_stream failed");
+        }
+        const long long nt = (long long)gp.n[0] * gp.n[0] + (long long)gp.n[1] * gp.n[1] +
+                             (long long)gp.n[2] * gp.n[2] + gp.n[0] + gp.n[1] + gp.n[2];
+        const unsigned nbt = (unsigned)((nt + 255) / 256);
+        if (d->prec == PPML_FP64)
+            k_grav_tables<double><<<nbt, 256, 0, g->stream>>>((double *)g->sx, (double *)g->sy, (double *)g->sz,
+                                                               g->fx, g->fy, g->fz, gp.n[0], gp.n[1], gp.n[2]);
+        else
+            k_grav_tables<float><<<nbt, 256, 0, g->stream>>>((float *)g->sx, (float *)g->sy, (float *)g->sz, g->fx,
+                                                              g->fy, g->fz, gp.n[0], gp.n[1], gp.n[2]);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+        if (e != hipSuccess) {
+            rocblas_destroy_handle(g->blas);
+            delete g;
+            return fail(PPML_EHIP, "self-gravity tables: %s", hipGetErrorString(e));
+        }
+    }
     g->gpE = gp;
     g->gpL = gp;
     if (d->ndim == 3) {
@@ -432,8 +620,8 @@ int ppml_create(const ppml_desc *d, void *state_dev, void *scratch_dev, void *hi
         // stage kernel (start-up cost: 3 z-only planes in the Eulerian
         // kernel, 6 in the Lagrangian kernel)
         long long se, sl;
-        if (d->prec == PPML_FP64) stage_slots<double>(g->device, d->tile, se, sl);
-        else stage_slots<float>(g->device, d->tile, se, sl);
+        if (d->prec == PPML_FP64) stage_slots<double>(g->device, d->tile, gp.self_grav != 0, se, sl);
+        else stage_slots<float>(g->device, d->tile, gp.self_grav != 0, se, sl);
         const long long txy = (long long)gp.tiles[0] * gp.tiles[1];
         set_chunks(g->gpE, choose_chunks(txy, gp.n[2], se, 1.5));
         set_chunks(g->gpL, choose_chunks(txy, gp.n[2], sl, 3.0));
@@ -544,9 +732,9 @@ int ppml_step(ppml_grid *g, int32_t nsteps, double dt_fixed, double t_stop)
     k_set_run<<<1, 1, 0, g->stream>>>(g->ctrl, dt_fixed, t_stop, (long long)nsteps);
     for (int s = 0; s < nsteps; s++) {
         hipEvent_t *ev = nullptr;
-        if ((size_t)(3 * (g->timed + 1)) <= g->ev.size()) ev = &g->ev[3 * g->timed];
-        if (g->d.prec == PPML_FP64) launch_step<double>(g, ev);
-        else launch_step<float>(g, ev);
+        if ((size_t)(4 * (g->timed + 1)) <= g->ev.size()) ev = &g->ev[4 * g->timed];
+        rc = g->d.prec == PPML_FP64 ? launch_step<double>(g, ev) : launch_step<float>(g, ev);
+        if (rc) return rc;
         if (ev) g->timed++;
     }
     HIPCHK(hipGetLastError());
@@ -647,7 +835,7 @@ int ppml_set_timing(ppml_grid *g, int32_t cap)
     for (hipEvent_t e : g->ev) (void)hipEventDestroy(e);
     g->ev.clear();
     g->timed = 0;
-    for (int i = 0; i < 3 * cap; i++) {
+    for (int i = 0; i < 4 * cap; i++) {
         hipEvent_t e;
         HIPCHK(hipEventCreate(&e));
         g->ev.push_back(e);
@@ -655,23 +843,56 @@ int ppml_set_timing(ppml_grid *g, int32_t cap)
     return PPML_OK;
 }
 
-int ppml_get_timing(ppml_grid *g, double *ms_euler, double *ms_lagr, int64_t *nsteps)
+int ppml_get_timing_split(ppml_grid *g, double ms[3], int64_t *nsteps)
 {
     int rc = grid_ok(g);
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(g->stream));
-    double me = 0.0, ml = 0.0;
-    for (long long s = 0; s < g->timed; s++) {
-        float a = 0.f, b = 0.f;
-        HIPCHK(hipEventElapsedTime(&a, g->ev[3 * s], g->ev[3 * s + 1]));
-        HIPCHK(hipEventElapsedTime(&b, g->ev[3 * s + 1], g->ev[3 * s + 2]));
-        me += a;
-        ml += b;
-    }
-    if (ms_euler) *ms_euler = me;
-    if (ms_lagr) *ms_lagr = ml;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (long long s = 0; s < g->timed; s++)
+        for (int q = 0; q < 3; q++) {
+            float a = 0.f;
+            HIPCHK(hipEventElapsedTime(&a, g->ev[4 * s + q], g->ev[4 * s + q + 1]));
+            acc[q] += a;
+        }
+    if (ms)
+        for (int q = 0; q < 3; q++) ms[q] = acc[q];
     if (nsteps) *nsteps = g->timed;
     g->timed = 0;
+    return PPML_OK;
+}
+
+int ppml_get_timing(ppml_grid *g, double *ms_euler, double *ms_lagr, int64_t *nsteps)
+{
+    double ms[3];
+    int rc = ppml_get_timing_split(g, ms, nsteps);
+    if (rc) return rc;
+    if (ms_euler) *ms_euler = ms[1];
+    if (ms_lagr) *ms_lagr = ms[2];
+    return PPML_OK;
+}
+
+int ppml_get_potential(ppml_grid *g, double *host_out)
+{
+    int rc = grid_ok(g);
+    if (rc) return rc;
+    if (!host_out) return fail(PPML_EINVAL, "host_out is NULL");
+    if (!g->gp.self_grav) return fail(PPML_EINVAL, "self-gravity is off for this grid");
+    if (!g->has_state) return fail(PPML_ESTATE, "state was never set");
+    if (g->in_batch) return fail(PPML_ESTATE, "grid is stepped by its batch");
+    rc = g->d.prec == PPML_FP64 ? launch_gravity<double>(g) : launch_gravity<float>(g);
+    if (rc) return rc;
+    const long long np = (long long)(g->gp.n[0] + 2) * (g->gp.n[1] + 2) * (g->gp.n[2] + 2);
+    double *tmp = nullptr;
+    HIPCHK(hipMalloc(&tmp, (size_t)np * sizeof(double)));
+    int nb = (int)std::min<long long>(4096, (np + 255) / 256);
+    if (g->d.prec == PPML_FP64) k_to_double<double><<<nb, 256, 0, g->stream>>>((const double *)g->phi, tmp, np);
+    else k_to_double<float><<<nb, 256, 0, g->stream>>>((const float *)g->phi, tmp, np);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(host_out, tmp, np * sizeof(double), hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(PPML_EHIP, "get_potential: %s", hipGetErrorString(e));
     return PPML_OK;
 }
 
@@ -681,6 +902,7 @@ int ppml_destroy(ppml_grid *g)
     if (g->in_batch) return fail(PPML_ESTATE, "retire the grid from its batch first");
     (void)hipStreamSynchronize(g->stream);
     for (hipEvent_t e : g->ev) (void)hipEventDestroy(e);
+    if (g->blas) rocblas_destroy_handle(g->blas);
     delete g;
     return PPML_OK;
 }
@@ -869,6 +1091,7 @@ int ppml_batch_admit(ppml_batch *b, ppml_grid *g, int32_t *slot)
     if (!g->has_state) return fail(PPML_ESTATE, "grid state was never set");
     if (g->device != b->device) return fail(PPML_EINVAL, "grid and batch live on different devices");
     if (b->prec >= 0 && g->d.prec != b->prec) return fail(PPML_EINVAL, "all grids of a batch share one precision");
+    if (g->gp.self_grav) return fail(PPML_EINVAL, "grids with self-gravity step alone, not in a batch");
     const size_t need = grid_bytes(g);
     if (b->budget > 0 && b->in_use + need > b->budget)
         return fail(PPML_EBUDGET, "admitting %zu bytes would exceed the budget (%zu of %zu in use)", need, b->in_use,

@@ -38,6 +38,9 @@ struct GridParams {
     int tiles[3];  // work-group tiles along x, y and z chunks of the stage kernels
     int cz;        // planes per z chunk (3-D)
     int any_inflow;  // some face has an inflow boundary (states in Ctrl::inflow)
+    int self_grav;   // 1: the force includes the gradient of the self-gravity potential
+    const void *phi; // that potential (storage type): interior cells plus a one-cell
+                     // shell, C order [k+1][j+1][i+1] with extents n+2
 };
 
 // Device control block of one grid (lives in the scratch area).  Every
@@ -62,6 +65,7 @@ struct Ctrl {
     int slot_l;           // slot_cur of the step in flight (for the Lagrangian kernel)
     int pad;
     double inflow[6][6];  // conserved ghost state of inflow face 2*axis+side (set once)
+    double mom[8];        // mass and second moments of the state (self-gravity boundary values)
 };
 
 #ifdef PPML_EXACT
@@ -354,6 +358,23 @@ __device__ __forceinline__ void potential_grad(const GridParams &gp, int i, int 
         g[0] = g[1] = g[2] = 0.0;
     }
     for (int a = gp.ndim; a < 3; a++) g[a] = 0.0;
+}
+
+// Adds the gradient of the self-gravity potential at interior cell (i, j, k):
+// the central difference across the cell (cubic cells, so h[0] serves
+// every axis).
+template <typename T>
+__device__ __forceinline__ void self_gravity_grad(const GridParams &gp, int i, int j, int k, double g[3])
+{
+    const T *ph = (const T *)gp.phi;
+    const long long px = gp.n[0] + 2;
+    const long long pp = px * (gp.n[1] + 2);
+    const long long b = (long long)(k + 1) * pp + (long long)(j + 1) * px + (i + 1);
+    const double h2 = 2.0 * gp.h[0];
+    const double ih2 = 0.5 * gp.inv_h[0];
+    g[0] = g[0] + PPML_DIV((double)ph[b + 1] - (double)ph[b - 1], h2, ih2);
+    g[1] = g[1] + PPML_DIV((double)ph[b + px] - (double)ph[b - px], h2, ih2);
+    g[2] = g[2] + PPML_DIV((double)ph[b + pp] - (double)ph[b - pp], h2, ih2);
 }
 
 // Time step of the next step (Sec. 2.1 CFL condition, or the fixed step),

@@ -187,7 +187,9 @@ __global__ __launch_bounds__(TOT_THREADS) void k_totals_final(const double *__re
 // ---------------------------------------------------------------------------
 // Eulerian stage
 // ---------------------------------------------------------------------------
-template <typename T, int NDIM, int TX, int TY>
+// SG: the grid has self-gravity (a separate instantiation, so the force's
+// loads of the potential cost the other grids no registers).
+template <typename T, int NDIM, int TX, int TY, bool SG = false>
 __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restrict__ Wst, const GridParams &gp,
                                            Ctrl *ctrl, const int bx, const int by, const int bz, const bool lead)
 {
@@ -508,9 +510,10 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
             mn[2] = mom[2] - tau * DPz;
             T Etn = Et - tau * sPV;
             T en = e - ((tau * gm1) * e) * sV;
-            if (gp.potential != POT_NONE) {
+            if (SG || gp.potential != POT_NONE) {
                 double g[3];
                 potential_grad(gp, gx, gy, k, g);
+                if constexpr (SG && NDIM == 3) self_gravity_grad<T>(gp, gx, gy, k, g);
                 const double work = (double)mom[0] * g[0] + (double)mom[1] * g[1] + (double)mom[2] * g[2];
                 const double tr = tau_d * (double)rho;
                 for (int ax = 0; ax < NDIM; ax++) mn[ax] = (T)((double)mn[ax] - tr * g[ax]);
@@ -526,13 +529,13 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
     }
 }
 
-template <typename T, int NDIM, int TX, int TY>
+template <typename T, int NDIM, int TX, int TY, bool SG = false>
 __global__ __launch_bounds__(TX *TY) void k_euler(const T *__restrict__ U, T *__restrict__ Wst, GridParams gp,
                                                    Ctrl *ctrl)
 {
     int bx, by, bz;
     block_tile(gp, bx, by, bz);
-    euler_body<T, NDIM, TX, TY>(U, Wst, gp, ctrl, bx, by, bz, blockIdx.x == 0 && threadIdx.x == 0);
+    euler_body<T, NDIM, TX, TY, SG>(U, Wst, gp, ctrl, bx, by, bz, blockIdx.x == 0 && threadIdx.x == 0);
 }
 
 // ---------------------------------------------------------------------------

@@ -34,7 +34,8 @@ class ppml_desc(C.Structure):
         ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("gamma", C.c_double), ("cfl", C.c_double),
         ("bc_lo", C.c_int32 * 3), ("bc_hi", C.c_int32 * 3), ("vacuum_ratio", C.c_double),
         ("potential", C.c_int32), ("flags", C.c_int32), ("pot", C.c_double * 8),
-        ("tile", C.c_int32), ("reserved", C.c_int32), ("inflow", (C.c_double * 5) * 6),
+        ("tile", C.c_int32), ("self_gravity", C.c_int32), ("inflow", (C.c_double * 5) * 6),
+        ("grav_G", C.c_double),
     ]
 
 
@@ -51,6 +52,7 @@ EXPORTS = (
     "ppml_destroy", "ppml_strerror", "ppml_last_error", "ppml_version", "ppml_set_timing", "ppml_get_timing",
     "ppml_batch_create", "ppml_batch_admit", "ppml_batch_retire", "ppml_batch_step", "ppml_batch_sync",
     "ppml_batch_info", "ppml_batch_destroy", "ppml_tile_count", "ppml_tile_shape", "ppml_batch_set_tile",
+    "ppml_get_potential", "ppml_get_timing_split",
 )
 
 _libs: dict[str, C.CDLL] = {}
@@ -85,6 +87,8 @@ def load(path: str | None = None) -> C.CDLL:
     lib.ppml_destroy.argtypes = [vp]
     lib.ppml_set_timing.argtypes = [vp, C.c_int32]
     lib.ppml_get_timing.argtypes = [vp, dp, dp, C.POINTER(C.c_int64)]
+    lib.ppml_get_timing_split.argtypes = [vp, dp, C.POINTER(C.c_int64)]
+    lib.ppml_get_potential.argtypes = [vp, dp]
     lib.ppml_batch_create.argtypes = [C.c_int32, C.c_size_t, vp, C.POINTER(vp)]
     lib.ppml_batch_admit.argtypes = [vp, vp, C.POINTER(C.c_int32)]
     lib.ppml_batch_retire.argtypes = [vp, C.c_int32]
@@ -114,7 +118,9 @@ def _check(lib, rc):
 
 
 def make_desc(ndim, n, lo, hi, gamma, cfl, bc="periodic", prec="fp64", vacuum_ratio=1e-5, potential=None,
-              first_order=False, tile=0, inflow=None):
+              first_order=False, tile=0, inflow=None, self_gravity=None):
+    """Descriptor of a grid; self_gravity = G > 0 turns on the self-gravity
+    potential (Sec. 2.5) with that gravitational constant."""
     d = ppml_desc()
     d.ndim = int(ndim)
     d.prec = PREC[prec] if isinstance(prec, str) else int(prec)
@@ -138,7 +144,8 @@ def make_desc(ndim, n, lo, hi, gamma, cfl, bc="periodic", prec="fp64", vacuum_ra
     d.potential = POT[potential[0]] if potential else PPML_POT_NONE
     d.flags = PPML_FLAG_FIRST_ORDER if first_order else 0
     d.tile = int(tile)
-    d.reserved = 0
+    d.self_gravity = 1 if self_gravity is not None else 0
+    d.grav_G = float(self_gravity) if self_gravity is not None else 0.0
     for face, st in (inflow or {}).items():  # face 2*axis+side -> (rho, vx, vy, vz, p)
         for q in range(5):
             d.inflow[int(face)][q] = float(st[q])
@@ -198,12 +205,12 @@ class Grid:
 
     def __init__(self, ndim, n, lo, hi, gamma, cfl, bc="periodic", prec="fp64", vacuum_ratio=1e-5,
                  potential=None, device="cuda", stream=None, exact=False, first_order=False, lib_path=None, tile=0,
-                 inflow=None):
+                 inflow=None, self_gravity=None):
         import torch
 
         self.lib = load(lib_path or (LIB_EXACT_PATH if exact else LIB_PATH))
         self.desc = make_desc(ndim, n, lo, hi, gamma, cfl, bc, prec, vacuum_ratio, potential, first_order, tile,
-                              inflow)
+                              inflow, self_gravity)
         self.ndim = int(ndim)
         self.ncell = int(self.desc.n[0] * self.desc.n[1] * self.desc.n[2])
         sb = ppml_state_bytes(self.desc, self.lib)
@@ -220,6 +227,7 @@ class Grid:
     @classmethod
     def from_problem(cls, prob, prec="fp64", exact=False, vacuum_ratio=1e-5, **kw):
         kw.setdefault("inflow", getattr(prob, "inflow", None))
+        kw.setdefault("self_gravity", getattr(prob, "self_gravity", None))
         g = cls(prob.ndim, prob.n, prob.lo, prob.hi, prob.gamma, prob.cfl, bc=prob.bc, prec=prec,
                 vacuum_ratio=vacuum_ratio, potential=prob.potential, exact=exact, **kw)
         g.set_primitive(prob.rho, prob.vx, prob.vy, prob.vz, prob.p)
@@ -285,6 +293,21 @@ class Grid:
         n = C.c_int64()
         _check(self.lib, self.lib.ppml_get_timing(self.h, C.byref(a), C.byref(b), C.byref(n)))
         return a.value, b.value, n.value
+
+    def get_timing_split(self):
+        """(ms gravity solve, ms Eulerian kernel, ms Lagrangian kernel, steps timed)."""
+        ms = (C.c_double * 3)()
+        n = C.c_int64()
+        _check(self.lib, self.lib.ppml_get_timing_split(self.h, ms, C.byref(n)))
+        return ms[0], ms[1], ms[2], n.value
+
+    def potential(self) -> np.ndarray:
+        """Self-gravity potential of the current state, shell included:
+        shape (nz+2, ny+2, nx+2), FP64."""
+        nz, ny, nx = self.shape
+        out = np.empty((nz + 2, ny + 2, nx + 2), dtype=np.float64)
+        _check(self.lib, self.lib.ppml_get_potential(self.h, _dp(out)))
+        return out
 
     def run_to(self, t_stop, chunk=64, max_steps=10 ** 7):
         """Step until t_stop (CFL steps, the last one clipped)."""

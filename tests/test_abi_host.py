@@ -108,11 +108,26 @@ def test_null_grid_rejected(lib):
     assert lib.ppml_destroy(None) == ppml.PPML_EINVAL
 
 
-def test_reserved_descriptor_field_must_be_zero(lib):
+def test_self_gravity_descriptor(lib):
+    """Self-gravity (Sec. 2.5) needs a 3-D grid of cubic cells and G > 0; the
+    scratch area grows by the padded potential, two work arrays and the sine
+    tables."""
     from paper_1607_01105_amd import ppml
 
-    d = _desc()
-    d.reserved = 1
+    cube = dict(n=(16, 8, 4), lo=(0, 0, 0), hi=(1.0, 0.5, 0.25))
+    for prec, e in (("fp32", 4), ("fp64", 8)):
+        d0 = _desc(prec=prec, **cube)
+        d1 = _desc(prec=prec, self_gravity=0.5, **cube)
+        extra = ppml.ppml_scratch_bytes(d1, lib) - ppml.ppml_scratch_bytes(d0, lib)
+        assert extra >= (18 * 10 * 6 + 2 * 16 * 8 * 4 + 16 * 16 + 8 * 8 + 4 * 4) * e + (16 + 8 + 4) * 8
+        assert ppml.ppml_state_bytes(d1, lib) == ppml.ppml_state_bytes(d0, lib)
+    for bad in (dict(self_gravity=0.5),                                   # cells 1/16 x 1/8 x 1/4
+                dict(self_gravity=0.0, **cube), dict(self_gravity=-1.0, **cube),
+                dict(self_gravity=1.0, ndim=2, n=(16, 16), lo=(0, 0), hi=(1, 1))):
+        assert ppml.ppml_state_bytes(_desc(**bad), lib) == 0, bad
+    d = _desc(**cube)
+    d.self_gravity = 2
+    d.grav_G = 1.0
     assert ppml.ppml_state_bytes(d, lib) == 0
 
 
