@@ -82,6 +82,8 @@ def load_library(path: str | None = None) -> C.CDLL:
     lib.og_max_threads.argtypes = []
     lib.og_set_threads.restype = None
     lib.og_set_threads.argtypes = [C.c_int]
+    lib.og_set_isothermal.restype = C.c_int
+    lib.og_set_isothermal.argtypes = [C.c_void_p, C.c_double]
     lib.og_set_self_gravity.restype = C.c_int
     lib.og_set_self_gravity.argtypes = [C.c_void_p, C.c_double]
     lib.og_multipole_moments.restype = None
@@ -160,12 +162,13 @@ class Oracle:
     ``inflow`` maps a face (2 * axis + side, side 0 low / 1 high) with an
     "inflow" boundary to its ghost state (rho, vx, vy, vz, p);
     ``self_gravity`` = G > 0 adds the force of the potential of the gas's own
-    mass (Sec. 2.5; 3-D, cubic cells).
+    mass (Sec. 2.5; 3-D, cubic cells); ``isothermal`` = cs > 0 selects the
+    isothermal variant p = cs^2 rho (Sec. 4).
     """
 
     def __init__(self, ndim, n, lo, hi, gamma, cfl, bc="periodic", vacuum_ratio=1e-5,
                  potential=None, first_order=False, lib: C.CDLL | str | None = None, inflow=None,
-                 self_gravity=None):
+                 self_gravity=None, isothermal=None):
         self.lib = lib if isinstance(lib, C.CDLL) else load_library(lib)
         self.ndim = int(ndim)
         n = list(n) + [1] * (3 - len(n))
@@ -195,6 +198,9 @@ class Oracle:
             raise ValueError("og_create failed")
         for face, st in (inflow or {}).items():
             self.lib.og_set_inflow(self.g, int(face), *[float(v) for v in st])
+        if isothermal is not None:
+            if self.lib.og_set_isothermal(self.g, float(isothermal)) != 0:
+                raise ValueError("isothermal sound speed must be > 0")
         if self_gravity is not None:
             if self.lib.og_set_self_gravity(self.g, float(self_gravity)) != 0:
                 raise ValueError("self-gravity needs a 3-D grid of cubic cells")

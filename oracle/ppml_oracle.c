@@ -25,6 +25,8 @@
  *   - density-weighted interface velocity, 9-point transverse
  *     velocity template, unsplit 3-D Lagrangian update          : Sec. 2.3, detailed algorithm
  *   - total-energy correction (dual energy)                     : Sec. 2.4
+ *   - self-gravity potential (27-point Poisson equation)        : Sec. 2.5
+ *   - isothermal variant (gamma = 1, p = cs^2 rho)               : Sec. 4, first paragraph
  *   - parabola construction and characteristic averages         : Appendix, steps 1-3
  *
  * Readings where the paper is silent or inconsistent (each listed in the
@@ -70,6 +72,8 @@ typedef struct {
     double *W[NF];   /* Eulerian-stage output U^{n+1/2}, ghosted           */
     double *acc[NF]; /* per-cell sums of directional differences           */
     double last_max_z_euler, last_max_z_lagr;
+    int iso;         /* 1: isothermal variant, p = cs^2 rho                 */
+    double cs;       /* its sound speed                                      */
     int self_grav;   /* 1: the self-gravity potential enters the force      */
     double grav_G;   /* gravitational constant of Delta Phi = 4 pi G rho    */
     double *phi;     /* potential on the interior plus a one-cell shell     */
@@ -373,8 +377,8 @@ void og_max_speeds(const og_grid *g, double *vmax, double *cmax)
                 double r = g->U[F_RHO][q];
                 double ux = g->U[F_MX][q] / r, uy = g->U[F_MY][q] / r, uz = g->U[F_MZ][q] / r;
                 double v = sqrt(ux * ux + uy * uy + uz * uz);
-                double p = (g->gamma - 1.0) * g->U[F_E][q];
-                double c = sqrt(g->gamma * p / r);
+                double p = g->iso ? (g->cs * g->cs) * r : (g->gamma - 1.0) * g->U[F_E][q];
+                double c = sqrt((g->iso ? 1.0 : g->gamma) * p / r);
                 if (v > vm) vm = v;
                 if (c > cm) cm = c;
             }
@@ -440,6 +444,21 @@ static void potential_grad(const og_grid *g, long i, long j, long k, double *gr)
 static long pidx(const og_grid *g, long i, long j, long k)
 {
     return ((k + 1) * (g->n[1] + 2) + (j + 1)) * (g->n[0] + 2) + (i + 1);
+}
+
+/* Isothermal variant (Sec. 4 adopts the isothermal approximation, gamma = 1):
+ * the pressure is cs^2 rho and the sound speed cs, in the Riemann problem and
+ * the CFL step.  The isothermal model has no energy equation; rho E and
+ * rho eps are carried along by the same updates (with gamma = 1 the eps
+ * equation loses its work term) but feed nothing back, and the vacuum branch
+ * of Sec. 2.4, which acts on them, is off.  0 or -1. */
+int og_set_isothermal(og_grid *g, double cs)
+{
+    if (!(cs > 0.0)) return -1;
+    g->iso = 1;
+    g->cs = cs;
+    g->vacuum_ratio = 0.0;
+    return 0;
 }
 
 /* Enable self-gravity with constant G (3-D, cubic cells).  0 or -1. */
@@ -707,7 +726,9 @@ static long line_base(const og_grid *g, int a, long l, long *ci, long *cj, long 
 /* ------------------------------------------------------------------------ */
 static void eulerian_stage(og_grid *g, double tau)
 {
-    const double gam = g->gamma;
+    /* isothermal variant: sound speeds and Riemann averages with gamma = 1,
+     * so the work term of the eps equation, (gamma - 1) rho eps div v, is 0 */
+    const double gam = g->iso ? 1.0 : g->gamma;
     long nc = ncell_ghosted(g);
     double **U = g->U;
     /* acc[0..2]: D^P_d per axis; acc[3]: sum_d D^{PV}_d; acc[4]: sum_d D^V_d */
@@ -732,7 +753,7 @@ static void eulerian_stage(og_grid *g, double tau)
                     qr[m] = r;
                     qs[m] = sqrt(r);
                     qv[m] = U[F_MX + a][q] / r;
-                    qp[m] = (gam - 1.0) * U[F_E][q];
+                    qp[m] = g->iso ? (g->cs * g->cs) * r : (gam - 1.0) * U[F_E][q];
                 }
                 recon(g, &b, 0, L); /* velocity parabolas */
                 recon(g, &b, 1, L); /* pressure parabolas */

@@ -50,6 +50,7 @@ class Problem:
     t_stop: float | None = None
     inflow: dict | None = None       # face (2 * axis + side) -> ghost state (rho, vx, vy, vz, p)
     self_gravity: float | None = None  # G of the self-gravity potential (Sec. 2.5), or None
+    isothermal: float | None = None    # sound speed of the isothermal variant (p = cs^2 rho), or None
 
     @property
     def shape(self):
@@ -106,6 +107,35 @@ def riemann_1d(seed: int, n: int = 512, lo: float = 0.0, hi: float = 1.0, x0: fl
                gamma: float = 1.4, cfl: float = 0.4, t_stop: float = 0.15, bc: str = "outflow") -> Problem:
     left, right = riemann_states(seed)
     return _two_state_1d(f"riemann1d_s{seed}_n{n}", left, right, n, lo, hi, x0, gamma, cfl, bc, t_stop)
+
+
+def isothermal_riemann(seed: int, n: int = 512, cs: float = 1.0, cfl: float = 0.4, t_stop: float = 0.15,
+                       gamma: float = 1.4) -> Problem:
+    """1-D Riemann problem of the isothermal variant (p = cs^2 rho) on [0, 1]:
+    rho_L, u_L, rho_R, u_R drawn in that order (rho ~ U[0.1, 1], u ~ U[-1, 1]),
+    interface at 0.5, outflow, CFL 0.4, t = 0.15.  The pressure array holds
+    cs^2 rho; gamma only sets the carried energy densities."""
+    rng = np.random.default_rng(seed)
+    rL, uL, rR, uR = rng.uniform(0.1, 1.0), rng.uniform(-1.0, 1.0), rng.uniform(0.1, 1.0), rng.uniform(-1.0, 1.0)
+    prob = _two_state_1d(f"iso_riemann1d_s{seed}_n{n}", (rL, uL, cs * cs * rL), (rR, uR, cs * cs * rR), n, 0.0, 1.0,
+                         0.5, gamma, cfl, "outflow", t_stop)
+    prob.isothermal = cs
+    return prob
+
+
+def isothermal_wave(n: int = 128, amp: float = 1e-3, cs: float = 0.7, cfl: float = 0.4, gamma: float = 1.4) -> Problem:
+    """Right-moving isothermal sound wave on the periodic unit interval:
+    rho = 1 + amp sin(2 pi x), u = cs amp sin(2 pi x) (the linear simple wave),
+    p = cs^2 rho; after t = 1 / cs it has travelled once round the interval."""
+    x = (np.arange(n) + 0.5) / n
+    d = amp * np.sin(2.0 * math.pi * x)
+    rho = (1.0 + d).reshape(1, 1, n)
+    u = (cs * d).reshape(1, 1, n)
+    z = np.zeros_like(rho)
+    prob = Problem(f"iso_wave_n{n}", 1, (n, 1, 1), (0.0, -0.5, -0.5), (1.0, 0.5, 0.5), gamma, cfl,
+                   [("periodic", "periodic")] * 3, rho, u, z.copy(), z.copy(), cs * cs * rho, None, None, 1.0 / cs)
+    prob.isothermal = cs
+    return prob
 
 
 # The paper's Table "Initial state of the shock tube problem":
@@ -228,12 +258,13 @@ def periodic_modes(n: int | tuple = 256, seed: int = 0, ndim: int = 3, gamma: fl
 
 def disk(nx: int = 512, ny: int = 512, nz: int = 64, seed: int = 0, v0: float = 1.0, rc: float = 0.02,
          rd: float = 0.2, cs: float = 0.05, gamma: float = 5.0 / 3.0, cfl: float = 0.2, nsteps: int = 500,
-         rho_floor: float = 1e-3, noise: float = 0.01) -> Problem:
+         rho_floor: float = 1e-3, noise: float = 0.01, isothermal: bool = False) -> Problem:
     """Rotating gas disk in Phi = v0^2/2 ln(rc^2 + x^2 + y^2 + z^2), box
     [-1/2,1/2]^2 x [-nz/(2 nx), nz/(2 nx)] (cubic cells): surface density
     exp(-R/rd), vertical Gaussian of scale height max(cs/v0 sqrt(R^2+rc^2), 2h),
     flat rotation v = v0 R / sqrt(R^2 + rc^2), p = rho cs^2 / gamma, 1% lognormal
-    density noise, outflow boundaries."""
+    density noise, outflow boundaries.  isothermal=True runs the paper's
+    isothermal approximation instead (p = cs^2 rho, the variant of Sec. 4)."""
     h = 1.0 / nx
     lo = (-0.5, -0.5 * ny * h, -0.5 * nz * h)
     hi = (0.5, 0.5 * ny * h, 0.5 * nz * h)
@@ -256,9 +287,14 @@ def disk(nx: int = 512, ny: int = 512, nz: int = 64, seed: int = 0, v0: float = 
     p = rho * cs * cs / gamma
     bc = [("outflow", "outflow")] * 3
     pot = ("log", v0, rc, 1.0, 0.0, 0.0, 0.0)
-    return Problem(f"disk_{nx}x{ny}x{nz}_s{seed}", 3, n3, lo, hi, gamma, cfl, bc,
+    if isothermal:
+        p = rho * cs * cs
+    iso = "_iso" if isothermal else ""
+    prob = Problem(f"disk_{nx}x{ny}x{nz}_s{seed}{iso}", 3, n3, lo, hi, gamma, cfl, bc,
                    np.ascontiguousarray(rho), np.ascontiguousarray(vx), np.ascontiguousarray(vy), vz,
                    np.ascontiguousarray(p), pot, nsteps, None)
+    prob.isothermal = cs if isothermal else None
+    return prob
 
 
 def gravity_sphere(n: int | tuple = 32, L: float = 2.0, G: float = 1.0, rho_floor: float = 1e-3,

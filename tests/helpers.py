@@ -15,7 +15,8 @@ def make_oracle(prob, lib=None, first_order=False, cfl=None, vacuum_ratio=1e-5):
     o = oracle.Oracle(prob.ndim, prob.n, prob.lo, prob.hi, prob.gamma, prob.cfl if cfl is None else cfl,
                       bc=prob.bc, vacuum_ratio=vacuum_ratio, potential=prob.potential,
                       first_order=first_order, lib=lib, inflow=getattr(prob, "inflow", None),
-                      self_gravity=getattr(prob, "self_gravity", None))
+                      self_gravity=getattr(prob, "self_gravity", None),
+                      isothermal=getattr(prob, "isothermal", None))
     o.set_primitive(prob.rho, prob.vx, prob.vy, prob.vz, prob.p)
     return o
 

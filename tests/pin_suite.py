@@ -819,6 +819,85 @@ def pin_self_gravity_force(lib=None):
     assert errs[1] < 6e-3 and errs[0] / errs[1] > 3.3, errs
 
 
+# --------------------------------------------------------------------------
+# Sec. 4: isothermal variant (gamma = 1, p = cs^2 rho)
+# --------------------------------------------------------------------------
+def pin_isothermal_riemann(lib=None, seeds=(0, 5, 11)):
+    """Seeded isothermal Riemann problems converge to the exact isothermal
+    solution (tests/exact_isothermal.py, written from the Rankine-Hugoniot
+    and Riemann-invariant relations)."""
+    import exact_isothermal as ei
+
+    for seed in seeds:
+        errs = []
+        for n in (128, 256, 512):
+            prob = W.isothermal_riemann(seed, n=n)
+            o = make_oracle(prob, lib=lib)
+            o.run(10 ** 6, t_stop=prob.t_stop)
+            left = (float(prob.rho.ravel()[0]), float(prob.vx.ravel()[0]))
+            right = (float(prob.rho.ravel()[-1]), float(prob.vx.ravel()[-1]))
+            ex = ei.cell_averages(left, right, prob.isothermal, 0.5, prob.t_stop, np.linspace(0.0, 1.0, n + 1), sub=8)
+            errs.append(l1(o.get("rho").ravel(), ex[0]))
+        assert errs[2] < errs[1] < errs[0] and errs[2] < 3e-3, (seed, errs)
+
+
+def pin_isothermal_sound_wave(lib=None):
+    """A small isothermal simple wave travels at cs (not sqrt(gamma) cs): after
+    one crossing time 1/cs the density profile returns to its start, with an
+    error that falls with the mesh."""
+    errs = []
+    for n in (64, 128, 256):
+        prob = W.isothermal_wave(n)
+        o = make_oracle(prob, lib=lib)
+        o.run(10 ** 6, t_stop=prob.t_stop)
+        errs.append(l1(o.get("rho").ravel(), prob.rho.ravel()) / 1e-3)
+    assert errs[2] < errs[1] < errs[0] and errs[2] < 0.05, errs
+
+
+def pin_isothermal_interface_sound_speed(lib=None):
+    """Sec. 2.1: with the modified Roe averages the sound speed at an interface
+    between rho = 1 and rho = 10^-4k of an isothermal gas is the gas's own
+    (Roe's averages would give about 10^k); the Eulerian Courant number is
+    cs tau / h to rounding, and the CFL sound speed is cs."""
+    cs = 0.8
+    for k in (1, 2):
+        n = 32
+        x = (np.arange(n) + 0.5) / n
+        rho = np.where(x < 0.5, 1.0, 10.0 ** (-4 * k)).reshape(1, 1, n)
+        z = np.zeros_like(rho)
+        o = oracle.Oracle(1, (n,), (0.0,), (1.0,), 1.4, 0.4, bc="outflow", lib=_lib(lib), isothermal=cs)
+        o.set_primitive(rho, z, None, None, cs * cs * rho)
+        vm, cm = o.max_speeds()
+        assert vm == 0.0 and abs(cm - cs) <= 1e-15 * cs, cm
+        tau = 1e-3
+        o.step(tau)
+        assert abs(o.last_max_z_euler - cs * tau * n) <= 1e-14 * cs * tau * n, (k, o.last_max_z_euler)
+
+
+def pin_isothermal_uniform_and_conservation(lib=None):
+    """Uniform isothermal states stay bit-exact; on a periodic 2-D box with
+    random blocks the isothermal variant conserves mass and momentum."""
+    for ndim in (1, 2, 3):
+        n = (12,) * ndim
+        o = oracle.Oracle(ndim, n, (0.0,) * ndim, (1.0,) * ndim, 1.4, 0.4, bc="periodic", lib=_lib(lib),
+                          isothermal=0.6)
+        shp = tuple(reversed(list(n) + [1] * (3 - ndim)))
+        rho = np.full(shp, 1.3)
+        o.set_primitive(rho, np.full(shp, 0.2), np.full(shp, -0.1), np.full(shp, 0.05), 0.36 * rho)
+        f0 = o.conserved()
+        o.run(5)
+        for f, a in zip(f0, o.conserved()):
+            assert np.array_equal(f, a), ndim
+    prob = W.blocks(2, (24, 20), seed=9)
+    prob.isothermal = 0.9
+    o = make_oracle(prob, lib=lib)
+    t0 = o.totals()
+    o.run(20)
+    t1 = o.totals()
+    for f in (0, 1, 2):
+        assert abs(t1[f] - t0[f]) <= 1e-13 * max(abs(t0[0]), 1.0), (f, t0[f], t1[f])
+
+
 # the workload pins run full problems of the paper's test section: last, so
 # that a planted mistake is usually caught by a quick pin first
 for _p in (pin_blast_waves_printed, pin_sedov_shock_radius, pin_kelvin_helmholtz_growth):

@@ -67,7 +67,7 @@ MUTANTS = [
     ("reflect_mirror", "return 2 * G - 1 - i; /* mirror */", "return 2 * G - i; /* mirror */"),
     ("cfl_sum", "return g->cfl * h / (vm + cm);", "return g->cfl * h / cm;"),
     ("cfl_h_max", "if (g->h[a] < h) h = g->h[a];", "if (g->h[a] > h) h = g->h[a];"),
-    ("pressure_eos", "qp[m] = (gam - 1.0) * U[F_E][q];", "qp[m] = gam * U[F_E][q];"),
+    ("pressure_eos", ": (gam - 1.0) * U[F_E][q];", ": gam * U[F_E][q];"),
     ("euler_h", "g->acc[a][q] = (Pi[j] - Pi[j - 1]) / h;", "g->acc[a][q] = (Pi[j] - Pi[j - 1]);"),
     ("inflow_side", "const double *st = g->inflow[2 * a + (i >= G + n ? 1 : 0)];",
      "const double *st = g->inflow[2 * a + (i >= G + n ? 0 : 1)];"),
@@ -87,6 +87,10 @@ MUTANTS = [
     ("gravity_gradient_h", "double h2 = 2.0 * g->h[0];", "double h2 = g->h[0];"),
     ("gravity_gradient_axis", "gr[1] = (g->phi[pidx(g, i, j + 1, k)] - g->phi[pidx(g, i, j - 1, k)]) / h2;",
      "gr[1] = (g->phi[pidx(g, i + 1, j, k)] - g->phi[pidx(g, i - 1, j, k)]) / h2;"),
+    ("iso_pressure", "qp[m] = g->iso ? (g->cs * g->cs) * r", "qp[m] = g->iso ? g->cs * r"),
+    ("iso_riemann_gamma", "const double gam = g->iso ? 1.0 : g->gamma;", "const double gam = g->gamma;"),
+    ("iso_cfl_speed", "double c = sqrt((g->iso ? 1.0 : g->gamma) * p / r);", "double c = sqrt(g->gamma * p / r);"),
+    ("iso_cfl_pressure", "double p = g->iso ? (g->cs * g->cs) * r :", "double p = g->iso ? g->cs * r :"),
 ]
 
 RUNNER = r"""
