@@ -195,18 +195,21 @@ def run_served(n_requests=60, load=0.5, seed=0, budget_gib=4.0, round_steps=50, 
             "data_wait_mean_s": st["data_wait_mean_s"], "tiles": {str(a): v for a, v in tiles.items()}}
 
 
-def run_disk(steps=500):
+def run_disk(steps=500, isothermal=False):
     """Rotating-disk configuration: 512 x 512 x 64, logarithmic potential,
     outflow, CFL 0.2, 500 steps.  FP32 (the configuration's state) and FP64,
-    each with its own CFL steps, with the L1 distance of the two densities."""
+    each with its own CFL steps, with the L1 distance of the two densities.
+    isothermal=True: the same disk in the isothermal variant (p = cs^2 rho,
+    the paper's approximation for its disks)."""
     import numpy as np
     import torch
 
     from paper_1607_01105_amd import workloads as W
     from paper_1607_01105_amd.ppml import Grid
 
-    prob = W.disk(nsteps=steps)
-    out = {"workload": "rotating gas disk 512x512x64 in a logarithmic potential, outflow, CFL 0.2, "
+    prob = W.disk(nsteps=steps, isothermal=isothermal)
+    kind = "isothermal (p = cs^2 rho, cs = 0.05)" if isothermal else "adiabatic (gamma = 5/3)"
+    out = {"workload": f"rotating gas disk 512x512x64, {kind}, in a logarithmic potential, outflow, CFL 0.2, "
                        f"{steps} steps", "cells": prob.cells, "steps": steps}
     for prec in ("fp32", "fp64"):
         g = Grid.from_problem(prob, prec=prec)
@@ -411,6 +414,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched and served runs")
     ap.add_argument("--serve-requests", type=int, default=60)
     ap.add_argument("--no-tune", action="store_true", help="use the default tile shape instead of the autotuner's")
+    ap.add_argument("--leg", choices=["gravity", "disk", "disk_isothermal", "suite", "batched"], default=None,
+                    help="run only this configuration (its JSON object, no headline line); for profiling")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one plain 256 MiB streaming kernel (torch.mul out-of-place: reads 256 MiB, "
                          "writes 256 MiB), the reference kernel for scaling the HBM byte counters")
@@ -433,6 +438,12 @@ def main():
         torch.cuda.synchronize()
         del a, b
         print("[bench] calibration copy: 268435456 bytes read, 268435456 bytes written", file=sys.stderr, flush=True)
+    if args.leg is not None:
+        legs = {"gravity": lambda: run_gravity(steps=args.steps), "disk": lambda: run_disk(steps=args.steps),
+                "disk_isothermal": lambda: run_disk(steps=args.steps, isothermal=True), "suite": run_suite,
+                "batched": lambda: run_batched(steps=args.steps)}
+        print(json.dumps({args.leg: legs[args.leg]()}))
+        return
     prob = W.periodic_modes(args.n, seed=0)
     cells = prob.cells
     res = {}
@@ -522,6 +533,9 @@ def main():
         out["disk"] = run_disk()
         print(f"[bench] disk: fp32 {out['disk']['fp32']['zone_updates_per_s']:.3e} zu/s, "
               f"fp64 {out['disk']['fp64']['zone_updates_per_s']:.3e} zu/s", file=sys.stderr, flush=True)
+        out["disk_isothermal"] = run_disk(isothermal=True)
+        print(f"[bench] isothermal disk: fp32 {out['disk_isothermal']['fp32']['zone_updates_per_s']:.3e} zu/s",
+              file=sys.stderr, flush=True)
         print("[bench] 1-D Riemann configuration", file=sys.stderr, flush=True)
         out["riemann_1d"] = run_riemann_1d()
         print("[bench] test-suite workloads", file=sys.stderr, flush=True)

@@ -72,8 +72,15 @@ typedef enum { PPML_POT_NONE = 0, PPML_POT_LOG = 1, PPML_POT_UNIFORM = 2 } ppml_
 
 /* Descriptor flags.  PPML_FLAG_FIRST_ORDER: piecewise-constant states in both
  * stages instead of parabolas -- the first-order scheme of Sec. 2.1 that the
- * paper compares against (its shock-tube comparison). */
-enum { PPML_FLAG_FIRST_ORDER = 1 };
+ * paper compares against (its shock-tube comparison).
+ * PPML_FLAG_ISOTHERMAL: the isothermal approximation the paper adopts for its
+ * galactic disks (Sec. 4, gamma = 1): pressure p = iso_cs^2 rho and sound
+ * speed iso_cs in the Riemann problem and the CFL step.  The isothermal model
+ * has no energy equation: rho E and rho eps are still stored (set from the
+ * given p with gamma as usual) and carried by the same updates -- with
+ * gamma = 1 the eps equation loses its work term -- but feed nothing back;
+ * the vacuum branch of Sec. 2.4, which acts on them, is off. */
+enum { PPML_FLAG_FIRST_ORDER = 1, PPML_FLAG_ISOTHERMAL = 2 };
 
 typedef struct {
     int32_t ndim;          /* 1, 2 or 3                                             */
@@ -99,6 +106,7 @@ typedef struct {
                               rho, p > 0; converted like ppml_set_primitive   */
     double grav_G;         /* gravitational constant G of Delta Phi = 4 pi G rho
                               (used when self_gravity = 1; > 0)                  */
+    double iso_cs;         /* sound speed of PPML_FLAG_ISOTHERMAL (> 0)             */
 } ppml_desc;
 
 /* Self-gravity (Sec. 2.5, the Poisson solver).  Before each step's Eulerian

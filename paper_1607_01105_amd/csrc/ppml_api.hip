@@ -118,7 +118,9 @@ int validate(const ppml_desc *d)
     if (d->potential != PPML_POT_NONE && d->potential != PPML_POT_LOG && d->potential != PPML_POT_UNIFORM)
         return fail(PPML_EINVAL, "bad potential code");
     if (d->potential == PPML_POT_LOG && !(d->pot[2] > 0.0)) return fail(PPML_EINVAL, "log potential needs q > 0");
-    if (d->flags & ~PPML_FLAG_FIRST_ORDER) return fail(PPML_EINVAL, "unknown flags 0x%x", d->flags);
+    if (d->flags & ~(PPML_FLAG_FIRST_ORDER | PPML_FLAG_ISOTHERMAL)) return fail(PPML_EINVAL, "unknown flags 0x%x", d->flags);
+    if ((d->flags & PPML_FLAG_ISOTHERMAL) && !(d->iso_cs > 0.0 && std::isfinite(d->iso_cs)))
+        return fail(PPML_EINVAL, "the isothermal variant needs iso_cs > 0");
     if (d->tile < 0 || d->tile >= NTILE[d->ndim])
         return fail(PPML_EINVAL, "tile %d out of range [0, %d) for ndim %d", d->tile, NTILE[d->ndim], d->ndim);
     if (d->self_gravity != 0 && d->self_gravity != 1) return fail(PPML_EINVAL, "self_gravity must be 0 or 1");
@@ -531,8 +533,17 @@ int ppml_create(const ppml_desc *d, void *state_dev, void *scratch_dev, void *hi
     }
     gp.ncell = ncells(d);
     gp.gamma = d->gamma;
+    if (d->flags & PPML_FLAG_ISOTHERMAL) {
+        gp.pa = d->iso_cs * d->iso_cs;
+        gp.pb = 0.0;
+        gp.gs = 1.0;
+    } else {
+        gp.pa = 0.0;
+        gp.pb = d->gamma - 1.0;
+        gp.gs = d->gamma;
+    }
     gp.cfl_hmin = d->cfl * hmin;
-    gp.vacuum_ratio = d->vacuum_ratio;
+    gp.vacuum_ratio = (d->flags & PPML_FLAG_ISOTHERMAL) ? 0.0 : d->vacuum_ratio;
     gp.potential = d->potential;
     gp.first_order = (d->flags & PPML_FLAG_FIRST_ORDER) ? 1 : 0;
     for (int i = 0; i < 8; i++) gp.pot[i] = d->pot[i];

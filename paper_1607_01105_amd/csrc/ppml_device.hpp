@@ -28,7 +28,11 @@ struct GridParams {
     long long ncell;
     double h[3], inv_h[3];
     double lo[3];
-    double gamma;
+    double gamma;         // ratio of specific heats (state conversions)
+    double pa, pb;        // pressure p = pa rho + pb rho eps: (0, gamma - 1), or
+                          // (cs^2, 0) in the isothermal variant; pb is also the
+                          // factor of the eps equation's work term
+    double gs;            // gamma of the sound speeds (1 in the isothermal variant)
     double cfl_hmin;      // cfl * min over active axes of h
     double vacuum_ratio;  // threshold relative to the initial mean density
     int bc_lo[3], bc_hi[3];

@@ -92,13 +92,13 @@ __global__ void k_set_run(Ctrl *ctrl, double dt_fixed, double t_stop, long long 
 
 // Per-cell speeds |v| and c (Sec. 2.1) of a conserved state.
 template <typename T, int NDIM>
-__device__ __forceinline__ void cell_speeds(T r, T mx, T my, T mz, T e, T gam, T gm1, T &v, T &c)
+__device__ __forceinline__ void cell_speeds(T r, T mx, T my, T mz, T e, T prho, T gam, T gm1, T &v, T &c)
 {
     T ux = mx / r;
     T uy = NDIM >= 2 ? my / r : T(0);
     T uz = NDIM >= 3 ? mz / r : T(0);
     v = dsqrt(ux * ux + uy * uy + uz * uz);
-    T p = gm1 * e;
+    T p = prho * r + gm1 * e;
     c = dsqrt(gam * p / r);
 }
 
@@ -118,7 +118,7 @@ __global__ void k_speeds(const T *__restrict__ U, GridParams gp, Ctrl *ctrl)
 {
     const int slot = ctrl->slot_cur;
     const long long N = gp.ncell;
-    const T gam = (T)gp.gamma, gm1 = (T)(gp.gamma - 1.0);
+    const T gam = (T)gp.gs, gm1 = (T)gp.pb, prho = (T)gp.pa;
     double vm = 0.0, cm = 0.0;
     for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x) {
         T r = U[c];
@@ -127,7 +127,7 @@ __global__ void k_speeds(const T *__restrict__ U, GridParams gp, Ctrl *ctrl)
         T mz = NDIM >= 3 ? U[3 * N + c] : T(0);
         T e = U[(2 + NDIM) * N + c];
         T v, cs;
-        cell_speeds<T, NDIM>(r, mx, my, mz, e, gam, gm1, v, cs);
+        cell_speeds<T, NDIM>(r, mx, my, mz, e, prho, gam, gm1, v, cs);
         vm = vm > (double)v ? vm : (double)v;
         cm = cm > (double)cs ? cm : (double)cs;
     }
@@ -237,8 +237,9 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
     }
     if (!(tau_d > 0.0)) return;
 
-    const T gam = (T)gp.gamma;
-    const T gm1 = (T)(gp.gamma - 1.0);
+    const T gam = (T)gp.gs;
+    const T gm1 = (T)gp.pb;
+    const T prho = (T)gp.pa;
     const T tau = (T)tau_d;
     const T hx = (T)gp.h[0], hy = (T)gp.h[1], hz = (T)gp.h[2];
     const T ihx = (T)gp.inv_h[0], ihy = (T)gp.inv_h[1], ihz = (T)gp.inv_h[2];
@@ -330,7 +331,7 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
                 }
             }
             const T vz = mzv / rho;
-            const T p = gm1 * e;
+            const T p = prho * rho + gm1 * e;
             const T s = dsqrt(rho);
             qv0 = qv1; qv1 = qv2; qv2 = vz;
             qp0 = qp1; qp1 = qp2; qp2 = p;
@@ -393,7 +394,7 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
                 s_vy[li] = myv * ir;
 #endif
             }
-            const T p = gm1 * e;
+            const T p = prho * rho + gm1 * e;
             const T s = dsqrt(rho);
             s_p[li] = p;
             s_s[li] = s;
@@ -427,7 +428,7 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
                     s_vy[li] = myv * ir;
 #endif
                 }
-                const T p = gm1 * e;
+                const T p = prho * rho + gm1 * e;
                 const T s = dsqrt(rho);
                 s_p[li] = p;
                 s_s[li] = s;
@@ -612,8 +613,9 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
     const int x0 = bx * TX, y0 = by * TY;
     const int nx = gp.n[0], ny = gp.n[1], nz = gp.n[2];
     const long long N = gp.ncell;
-    const T gam = (T)gp.gamma;
-    const T gm1 = (T)(gp.gamma - 1.0);
+    const T gam = (T)gp.gs;
+    const T gm1 = (T)gp.pb;
+    const T prho = (T)gp.pa;
     const T tau = (T)tau_d;
     const T hx = (T)gp.h[0], hy = (T)gp.h[1], hz = (T)gp.h[2];
     const T ihx = (T)gp.inv_h[0], ihy = (T)gp.inv_h[1], ihz = (T)gp.inv_h[2];
@@ -1153,8 +1155,8 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
 #pragma unroll
             for (int f = 0; f < NF; f++) U[(size_t)f * (size_t)N + c] = fn[f];
             T v, cs;
-            cell_speeds<T, NDIM>(fn[0], fn[1], NDIM >= 2 ? fn[2] : T(0), NDIM >= 3 ? fn[3] : T(0), fn[NDIM + 2], gam,
-                                 gm1, v, cs);
+            cell_speeds<T, NDIM>(fn[0], fn[1], NDIM >= 2 ? fn[2] : T(0), NDIM >= 3 ? fn[3] : T(0), fn[NDIM + 2], prho,
+                                 gam, gm1, v, cs);
             const bool bad = !(fn[0] > T(0)) || !(fn[NDIM + 2] > T(0)) || !(v == v) || !(cs == cs) ||
                              __builtin_isinf((double)v) || __builtin_isinf((double)fn[NDIM + 1]);
             if (bad) atomicOr(&ctrl->err, 1);

@@ -21,7 +21,7 @@ PPML_FP32, PPML_FP64 = 0, 1
 PPML_PERIODIC, PPML_OUTFLOW, PPML_REFLECT, PPML_INFLOW = 0, 1, 2, 3
 PPML_RHO, PPML_MX, PPML_MY, PPML_MZ, PPML_ETOT, PPML_EINT = 0, 1, 2, 3, 4, 5
 PPML_POT_NONE, PPML_POT_LOG, PPML_POT_UNIFORM = 0, 1, 2
-PPML_FLAG_FIRST_ORDER = 1
+PPML_FLAG_FIRST_ORDER, PPML_FLAG_ISOTHERMAL = 1, 2
 
 BC = {"periodic": PPML_PERIODIC, "outflow": PPML_OUTFLOW, "reflect": PPML_REFLECT, "inflow": PPML_INFLOW}
 PREC = {"fp32": PPML_FP32, "f32": PPML_FP32, "fp64": PPML_FP64, "f64": PPML_FP64}
@@ -35,7 +35,7 @@ class ppml_desc(C.Structure):
         ("bc_lo", C.c_int32 * 3), ("bc_hi", C.c_int32 * 3), ("vacuum_ratio", C.c_double),
         ("potential", C.c_int32), ("flags", C.c_int32), ("pot", C.c_double * 8),
         ("tile", C.c_int32), ("self_gravity", C.c_int32), ("inflow", (C.c_double * 5) * 6),
-        ("grav_G", C.c_double),
+        ("grav_G", C.c_double), ("iso_cs", C.c_double),
     ]
 
 
@@ -118,9 +118,10 @@ def _check(lib, rc):
 
 
 def make_desc(ndim, n, lo, hi, gamma, cfl, bc="periodic", prec="fp64", vacuum_ratio=1e-5, potential=None,
-              first_order=False, tile=0, inflow=None, self_gravity=None):
+              first_order=False, tile=0, inflow=None, self_gravity=None, isothermal=None):
     """Descriptor of a grid; self_gravity = G > 0 turns on the self-gravity
-    potential (Sec. 2.5) with that gravitational constant."""
+    potential (Sec. 2.5) with that gravitational constant; isothermal = cs > 0
+    selects the isothermal variant p = cs^2 rho (Sec. 4)."""
     d = ppml_desc()
     d.ndim = int(ndim)
     d.prec = PREC[prec] if isinstance(prec, str) else int(prec)
@@ -142,7 +143,8 @@ def make_desc(ndim, n, lo, hi, gamma, cfl, bc="periodic", prec="fp64", vacuum_ra
     d.cfl = float(cfl)
     d.vacuum_ratio = float(vacuum_ratio)
     d.potential = POT[potential[0]] if potential else PPML_POT_NONE
-    d.flags = PPML_FLAG_FIRST_ORDER if first_order else 0
+    d.flags = (PPML_FLAG_FIRST_ORDER if first_order else 0) | (PPML_FLAG_ISOTHERMAL if isothermal is not None else 0)
+    d.iso_cs = float(isothermal) if isothermal is not None else 0.0
     d.tile = int(tile)
     d.self_gravity = 1 if self_gravity is not None else 0
     d.grav_G = float(self_gravity) if self_gravity is not None else 0.0
@@ -205,12 +207,12 @@ class Grid:
 
     def __init__(self, ndim, n, lo, hi, gamma, cfl, bc="periodic", prec="fp64", vacuum_ratio=1e-5,
                  potential=None, device="cuda", stream=None, exact=False, first_order=False, lib_path=None, tile=0,
-                 inflow=None, self_gravity=None):
+                 inflow=None, self_gravity=None, isothermal=None):
         import torch
 
         self.lib = load(lib_path or (LIB_EXACT_PATH if exact else LIB_PATH))
         self.desc = make_desc(ndim, n, lo, hi, gamma, cfl, bc, prec, vacuum_ratio, potential, first_order, tile,
-                              inflow, self_gravity)
+                              inflow, self_gravity, isothermal)
         self.ndim = int(ndim)
         self.ncell = int(self.desc.n[0] * self.desc.n[1] * self.desc.n[2])
         sb = ppml_state_bytes(self.desc, self.lib)
@@ -228,6 +230,7 @@ class Grid:
     def from_problem(cls, prob, prec="fp64", exact=False, vacuum_ratio=1e-5, **kw):
         kw.setdefault("inflow", getattr(prob, "inflow", None))
         kw.setdefault("self_gravity", getattr(prob, "self_gravity", None))
+        kw.setdefault("isothermal", getattr(prob, "isothermal", None))
         g = cls(prob.ndim, prob.n, prob.lo, prob.hi, prob.gamma, prob.cfl, bc=prob.bc, prec=prec,
                 vacuum_ratio=vacuum_ratio, potential=prob.potential, exact=exact, **kw)
         g.set_primitive(prob.rho, prob.vx, prob.vy, prob.vz, prob.p)

@@ -1,0 +1,157 @@
+"""The isothermal variant (Sec. 4: gamma = 1, p = cs^2 rho) on the GPU,
+through the C ABI, against the FP64 oracle's isothermal mode.
+
+* exact build: FP64 results, time and step count equal the oracle's bit for
+  bit (1-D Riemann problems with the GPU's own CFL steps, 2-D and 3-D blocks
+  with every boundary kind, a potential, the disk);
+* product build: FP64 within 1e-12 per field, FP32 within 1e-4 (L1, density)
+  driven by the oracle's time steps; the full-size isothermal disk, one step,
+  every cell;
+* every tile shape gives the same bits; batches equal solo runs.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from helpers import make_oracle
+from paper_1607_01105_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _grid(prob, prec="fp64", exact=False, **kw):
+    from paper_1607_01105_amd.ppml import Grid
+
+    print(f"[case] {prob.name} prec={prec} exact={exact} {kw}", flush=True)
+    return Grid.from_problem(prob, prec=prec, exact=exact, **kw)
+
+
+def _fields(ndim):
+    return [0] + [1 + a for a in range(ndim)] + [4, 5]
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+
+
+def _iso(prob, cs, bc=None):
+    prob.isothermal = cs
+    prob.p = cs * cs * prob.rho
+    if bc is not None:
+        prob.bc = bc
+    prob.name += f"_iso{cs}"
+    return prob
+
+
+def _cases():
+    return [
+        ("blocks2d_periodic", _iso(W.blocks(2, (37, 23), seed=31), 0.7)),
+        ("blocks2d_reflect", _iso(W.blocks(2, (29, 33), seed=32, bc="reflect"), 1.1)),
+        ("blocks3d_outflow", _iso(W.blocks(3, (19, 13, 21), seed=33, bc="outflow"), 0.5)),
+        ("smooth3d_mixed_uniformg", _iso(W.random_smooth(3, (24, 20, 18), seed=34), 0.9,
+                                         [("reflect", "outflow"), ("periodic", "periodic"), ("outflow", "reflect")])),
+        ("disk_small", W.disk(64, 64, 16, seed=3, isothermal=True)),
+    ]
+
+
+CASES = _cases()
+CASES[3][1].potential = ("uniform", 0.0, 0.0, -0.4)
+
+
+@pytest.mark.parametrize("seed", [0, 3, 7, 12])
+def test_exact_bitwise_isothermal_riemann(seed):
+    prob = W.isothermal_riemann(seed)
+    o = make_oracle(prob)
+    taus = o.run(10 ** 6, t_stop=prob.t_stop)
+    g = _grid(prob, exact=True)
+    t, dt, steps = g.run_to(prob.t_stop)
+    assert steps == len(taus) and t == o.t and dt == taus[-1]
+    for f in _fields(1):
+        assert np.array_equal(g.get(f), o.get(f)), f
+
+
+@pytest.mark.parametrize("name,prob", CASES, ids=[c[0] for c in CASES])
+def test_exact_bitwise_isothermal_multid(name, prob):
+    o = make_oracle(prob)
+    taus = o.run(10)
+    g = _grid(prob, exact=True)
+    g.step(10)
+    t, dt, steps = g.time()
+    assert steps == 10 and t == o.t and dt == taus[-1]
+    for f in _fields(prob.ndim):
+        a, b = g.get(f), o.get(f)
+        assert np.array_equal(a, b), (name, f, int(np.sum(a != b)))
+
+
+@pytest.mark.parametrize("name,prob", CASES, ids=[c[0] for c in CASES])
+def test_product_isothermal_fp64_fp32(name, prob):
+    o = make_oracle(prob)
+    taus = o.run(10)
+    g = _grid(prob)
+    g.step(10)
+    for f in _fields(prob.ndim):
+        err = _rel(g.get(f), o.get(f))
+        assert err <= 1e-12, (name, f, err)
+    g32 = _grid(prob, prec="fp32")
+    for tau in taus:
+        g32.step(1, dt_fixed=float(tau))
+    r64 = o.get("rho")
+    l1 = float(np.sum(np.abs(g32.get("rho") - r64)) / np.sum(r64))
+    print(f"{name} fp32 L1(rho) {l1:.3e}", flush=True)
+    assert l1 <= 1e-4
+
+
+def test_isothermal_full_size_disk_one_step():
+    """The isothermal disk at the disk workload's full 512 x 512 x 64 size: one
+    step, every cell: FP64 within 1e-12, FP32 within 1e-5 on the density and
+    momenta (the fields the isothermal model evolves); the carried energy
+    densities within the disk's FP32 Mach-20 cancellation bound 2e-4."""
+    prob = W.disk(seed=0, isothermal=True)
+    o = make_oracle(prob)
+    tau = o.dt()
+    o.step(tau)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        g = _grid(prob, prec=prec)
+        g.step(1, dt_fixed=tau)
+        for f in range(6):
+            err = _rel(g.get(f), o.get(f))
+            bound = 2e-4 if (prec == "fp32" and f >= 4) else tol
+            print(f"iso disk full size {prec} field {f}: rel err {err:.3e}", flush=True)
+            assert err <= bound, (prec, f, err)
+        del g
+
+
+def test_isothermal_tiles_and_batch():
+    from paper_1607_01105_amd.ppml import Batch, ppml_tile_count
+
+    probs = [CASES[0][1], CASES[2][1], W.isothermal_riemann(5, n=300)]
+    for p in probs:
+        ref = None
+        for v in range(ppml_tile_count(p.ndim)):
+            g = _grid(p, prec="fp32", tile=v)
+            g.step(6)
+            out = [g.get(f) for f in _fields(p.ndim)]
+            if ref is None:
+                ref = out
+            for a, b in zip(out, ref):
+                assert np.array_equal(a, b), (p.name, v)
+    b = Batch(capacity=4)
+    mixed = probs + [W.blocks(2, (20, 30), seed=35)]
+    slots = [b.admit(b.new_grid(p, prec="fp32")) for p in mixed]
+    b.step(6, graph=True)
+    b.sync()
+    for p, s in zip(mixed, slots):
+        solo = _grid(p, prec="fp32")
+        solo.step(6)
+        for f in _fields(p.ndim):
+            assert np.array_equal(b.grids[s].get(f), solo.get(f)), (p.name, f)
