@@ -316,7 +316,9 @@ template <typename T> int launch_gravity(ppml_grid *g)
     const long long nshell = (long long)(n0 + 2) * (n1 + 2) * (n2 + 2) - N;
     k_grav_shell<T><<<(unsigned)((nshell + 255) / 256), 256, 0, g->stream>>>(gp, g->ctrl, g->d.grav_G, phi);
     const unsigned nbc = (unsigned)((N + 255) / 256);
-    k_grav_rhs<T><<<nbc, 256, 0, g->stream>>>(rho, phi, gp, g->grav_coef, X);
+    k_grav_rhs<T><<<nbc, 256, 0, g->stream>>>(rho, gp, g->grav_coef, X);
+    const long long nedge = grav_edge_cells(n0, n1, n2);
+    k_grav_rhs_edge<T><<<(unsigned)((nedge + 255) / 256), 256, 0, g->stream>>>(rho, phi, gp, g->grav_coef, X);
     HIPCHK(hipGetLastError());
     int rc;
     if ((rc = sine_transform<T>(g, 0, X, Y))) return rc;

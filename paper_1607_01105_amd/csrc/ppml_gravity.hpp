@@ -67,14 +67,19 @@ __global__ void k_grav_tables(T *__restrict__ Sx, T *__restrict__ Sy, T *__restr
     S[q] = (T)sinpi((double)m / (double)(n + 1));
 }
 
-// Interior cell index -> (i, j, k) and its centre.
+// Interior cell index -> (i, j, k).  Grids hold fewer than 2^31 cells, so
+// 32-bit unsigned division serves (64-bit division is a long software
+// sequence on the GPU).
 __device__ __forceinline__ void cell_of(const GridParams &gp, long long c, int &i, int &j, int &k)
 {
-    const long long n0 = gp.n[0], n01 = n0 * gp.n[1];
-    k = (int)(c / n01);
-    const long long r = c - (long long)k * n01;
-    j = (int)(r / n0);
-    i = (int)(r - (long long)j * n0);
+    const unsigned n0 = (unsigned)gp.n[0], n01 = n0 * (unsigned)gp.n[1];
+    const unsigned cu = (unsigned)c;
+    const unsigned kk = cu / n01;
+    const unsigned r = cu - kk * n01;
+    const unsigned jj = r / n0;
+    k = (int)kk;
+    j = (int)jj;
+    i = (int)(r - jj * n0);
 }
 
 __device__ __forceinline__ double block_sum(double v, double *sh)
@@ -185,19 +190,54 @@ __global__ void k_grav_shell(GridParams gp, const Ctrl *__restrict__ ctrl, doubl
     phi[pad_index(gp, i, j, k)] = (T)v;
 }
 
-// Right-hand side of the interior cells: coef rho (coef = 4 pi G h^2) minus
-// the stencil's weight times every shell value the cell's stencil touches.
+// Right-hand side of the interior cells, first pass: coef rho (coef =
+// 4 pi G h^2) everywhere (a plain stream).
 template <typename T>
-__global__ void k_grav_rhs(const T *__restrict__ rho, const T *__restrict__ phi, GridParams gp, double coef,
-                           T *__restrict__ X)
+__global__ void k_grav_rhs(const T *__restrict__ rho, GridParams gp, double coef, T *__restrict__ X)
 {
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= gp.ncell) return;
-    int i, j, k;
-    cell_of(gp, c, i, j, k);
+    X[c] = (T)(coef * (double)rho[c]);
+}
+
+// Second pass over the outer layer of interior cells only (the two z
+// planes, the two y rows of the other planes, the two x ends of the other
+// rows; a cell listed twice on a grid of extent 1 or 2 gets the same value
+// twice): coef rho minus the stencil's weight times every shell value the
+// cell's stencil touches, in the stencil's (dz, dy, dx) order.
+template <typename T>
+__global__ void k_grav_rhs_edge(const T *__restrict__ rho, const T *__restrict__ phi, GridParams gp, double coef,
+                                T *__restrict__ X)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int n0 = gp.n[0], n1 = gp.n[1], n2 = gp.n[2];
+    const long long P = (long long)n0 * n1;
+    const int m2 = n2 > 2 ? n2 - 2 : 0, m1 = n1 > 2 ? n1 - 2 : 0;
+    const long long nA = 2 * P, nB = 2ll * m2 * n0, nC = 2ll * m2 * m1;
+    int i, j, k;
+    if (s < nA) {
+        k = (s / P) ? n2 - 1 : 0;
+        const long long r = s % P;
+        j = (int)(r / n0);
+        i = (int)(r % n0);
+    } else if (s < nA + nB) {
+        const long long t = s - nA;
+        const long long row = t / n0;
+        k = 1 + (int)(row / 2);
+        j = (row % 2) ? n1 - 1 : 0;
+        i = (int)(t % n0);
+    } else if (s < nA + nB + nC) {
+        const long long t = s - nA - nB;
+        k = 1 + (int)(t / (2 * m1));
+        const long long r = t % (2 * m1);
+        j = 1 + (int)(r / 2);
+        i = (r % 2) ? n0 - 1 : 0;
+    } else {
+        return;
+    }
+    const long long c = ((long long)k * n1 + j) * n0 + i;
     double b = coef * (double)rho[c];
-    if (i == 0 || j == 0 || k == 0 || i == n0 - 1 || j == n1 - 1 || k == n2 - 1) {
+    {
         for (int dz = -1; dz <= 1; dz++)
             for (int dy = -1; dy <= 1; dy++)
                 for (int dx = -1; dx <= 1; dx++) {
@@ -209,6 +249,13 @@ __global__ void k_grav_rhs(const T *__restrict__ rho, const T *__restrict__ phi,
                 }
     }
     X[c] = (T)b;
+}
+
+// Cells of the outer layer listed by k_grav_rhs_edge.
+inline long long grav_edge_cells(int n0, int n1, int n2)
+{
+    const long long m2 = n2 > 2 ? n2 - 2 : 0, m1 = n1 > 2 ? n1 - 2 : 0;
+    return 2ll * n0 * n1 + 2ll * m2 * n0 + 2ll * m2 * m1;
 }
 
 // Stage 3: amplitude / eigenvalue times the inverse transform's factor.
