@@ -366,6 +366,43 @@ def run_gravity(n=256, steps=50):
     return out
 
 
+def run_galaxy(steps=20, sizes=((256, ("fp32", "fp64")), (512, ("fp32",)))):
+    """The paper's galactic-disk configuration with synthetic data (Sec. 4:
+    isothermal gas, self-gravity, fixed halo potential, CFL 0.2), on 256^3
+    (FP32 and FP64) and on the paper's 512^3 mesh (FP32): zone-updates/s of
+    whole steps (potential solve + both stage kernels) and the split."""
+    import torch
+
+    from paper_1607_01105_amd import workloads as W
+    from paper_1607_01105_amd.ppml import Grid
+
+    out = {"workload": "isothermal self-gravitating disk (cs = 0.05, G = 1) in a logarithmic halo potential, "
+                       f"box [-1/2,1/2]^3, outflow, CFL 0.2, {steps} steps"}
+    for n, precs in sizes:
+        prob = W.galaxy_disk(n)
+        out[str(n)] = {}
+        for prec in precs:
+            g = Grid.from_problem(prob, prec=prec)
+            g.step(2)
+            g.sync()
+            g.set_timing(steps)
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record(g.stream)
+            g.step(steps)
+            t1.record(g.stream)
+            g.sync()
+            ms = t0.elapsed_time(t1)
+            mg, me, ml, k = g.get_timing_split()
+            out[str(n)][prec] = {"zone_updates_per_s": prob.cells * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+                                 "split_ms": {"gravity": mg / k, "euler": me / k, "lagr": ml / k}}
+            _log(f"[bench] galaxy {n}^3 {prec}: {ms / steps:.3f} ms/step (gravity {mg / k:.3f} ms)")
+            del g
+            torch.cuda.empty_cache()
+        del prob
+    return out
+
+
 def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -414,7 +451,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched and served runs")
     ap.add_argument("--serve-requests", type=int, default=60)
     ap.add_argument("--no-tune", action="store_true", help="use the default tile shape instead of the autotuner's")
-    ap.add_argument("--leg", choices=["gravity", "disk", "disk_isothermal", "suite", "batched"], default=None,
+    ap.add_argument("--leg", choices=["gravity", "galaxy", "disk", "disk_isothermal", "suite", "batched"], default=None,
                     help="run only this configuration (its JSON object, no headline line); for profiling")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one plain 256 MiB streaming kernel (torch.mul out-of-place: reads 256 MiB, "
@@ -441,7 +478,7 @@ def main():
     if args.leg is not None:
         legs = {"gravity": lambda: run_gravity(steps=args.steps), "disk": lambda: run_disk(steps=args.steps),
                 "disk_isothermal": lambda: run_disk(steps=args.steps, isothermal=True), "suite": run_suite,
-                "batched": lambda: run_batched(steps=args.steps)}
+                "batched": lambda: run_batched(steps=args.steps), "galaxy": lambda: run_galaxy(steps=args.steps)}
         print(json.dumps({args.leg: legs[args.leg]()}))
         return
     prob = W.periodic_modes(args.n, seed=0)
@@ -542,6 +579,8 @@ def main():
         out["suite"] = run_suite()
         print("[bench] self-gravity workload", file=sys.stderr, flush=True)
         out["gravity"] = run_gravity()
+        print("[bench] galactic-disk configuration", file=sys.stderr, flush=True)
+        out["galaxy"] = run_galaxy()
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob)

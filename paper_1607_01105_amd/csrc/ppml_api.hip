@@ -259,43 +259,57 @@ template <typename T, int NDIM> void launch_stages(ppml_grid *g, hipEvent_t *ev)
 
 // GEMMs of the sine transforms (column-major view of the C-order arrays:
 // a matrix with leading dimension n0 has the x index as its row).
-rocblas_status gemm(rocblas_handle h, int m, int n, int k, const float *A, int lda, long long sa, const float *B,
-                    int ldb, long long sb, float *C, int ldc, long long sc, int batch)
+rocblas_status gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k, const float *A,
+                    int lda, long long sa, const float *B, int ldb, long long sb, float *C, int ldc, long long sc,
+                    int batch)
 {
     const float one = 1.0f, zero = 0.0f;
-    if (batch == 1)
-        return rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_none, m, n, k, &one, A, lda, B, ldb, &zero,
-                             C, ldc);
-    return rocblas_sgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, m, n, k, &one, A, lda, sa,
-                                         B, ldb, sb, &zero, C, ldc, sc, batch);
+    if (batch == 1) return rocblas_sgemm(h, ta, tb, m, n, k, &one, A, lda, B, ldb, &zero, C, ldc);
+    return rocblas_sgemm_strided_batched(h, ta, tb, m, n, k, &one, A, lda, sa, B, ldb, sb, &zero, C, ldc, sc, batch);
 }
 
-rocblas_status gemm(rocblas_handle h, int m, int n, int k, const double *A, int lda, long long sa, const double *B,
-                    int ldb, long long sb, double *C, int ldc, long long sc, int batch)
+rocblas_status gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
+                    const double *A, int lda, long long sa, const double *B, int ldb, long long sb, double *C, int ldc,
+                    long long sc, int batch)
 {
     const double one = 1.0, zero = 0.0;
-    if (batch == 1)
-        return rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, m, n, k, &one, A, lda, B, ldb, &zero,
-                             C, ldc);
-    return rocblas_dgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, m, n, k, &one, A, lda, sa,
-                                         B, ldb, sb, &zero, C, ldc, sc, batch);
+    if (batch == 1) return rocblas_dgemm(h, ta, tb, m, n, k, &one, A, lda, B, ldb, &zero, C, ldc);
+    return rocblas_dgemm_strided_batched(h, ta, tb, m, n, k, &one, A, lda, sa, B, ldb, sb, &zero, C, ldc, sc, batch);
 }
 
-// Sine transform of every line of one axis: x (C = Sx A over the n1 n2
-// columns), y (per plane: C_k = A_k Sy), z (C = A Sz over the n0 n1 rows).
-// Sine matrices are symmetric.
-template <typename T> int sine_transform(ppml_grid *g, int axis, const T *A, T *C)
+// Sine transform of every line of one axis, on data in (sum | difference)
+// slots along that axis: the odd modes are So times the sums, the even
+// modes Se times the differences (forward); back, the sums are So^T times
+// the odd modes and the differences Se^T times the even modes.  Column-major
+// views of the C-order arrays: x as rows (C = op(S) A over the n1 n2
+// columns), y per plane (C_k = A_k op(S)^T, a strided batch over the n2
+// planes), z as columns (C = A op(S)^T over the n0 n1 rows).
+template <typename T> int sine_transform(ppml_grid *g, int axis, bool inverse, const T *A, T *C)
 {
-    const int n0 = g->gp.n[0], n1 = g->gp.n[1], n2 = g->gp.n[2];
-    rocblas_status st;
-    if (axis == 0)
-        st = gemm(g->blas, n0, n1 * n2, n0, (const T *)g->sx, n0, 0, A, n0, 0, C, n0, 0, 1);
-    else if (axis == 1)
-        st = gemm(g->blas, n0, n1, n1, A, n0, (long long)n0 * n1, (const T *)g->sy, n1, 0, C, n0, (long long)n0 * n1,
-                  n2);
-    else
-        st = gemm(g->blas, n0 * n1, n2, n2, A, n0 * n1, 0, (const T *)g->sz, n2, 0, C, n0 * n1, 0, 1);
-    if (st != rocblas_status_success) return fail(PPML_EHIP, "rocBLAS GEMM of the sine transform: status %d", (int)st);
+    const int n[3] = {g->gp.n[0], g->gp.n[1], g->gp.n[2]};
+    const int na = n[axis];
+    const int no = grav_no(na), ne = grav_ne(na);
+    const T *S = (const T *)(axis == 0 ? g->sx : axis == 1 ? g->sy : g->sz);
+    const rocblas_operation N_ = rocblas_operation_none, T_ = rocblas_operation_transpose;
+    const long long plane = (long long)n[0] * n[1];
+    for (int half = 0; half < 2; half++) {
+        const int m = half ? ne : no;             // slots of this half
+        if (m == 0) continue;
+        const T *Sh = S + (half ? (long long)no * no : 0);  // m x m, column major
+        const long long off = half ? no : 0;      // first slot of the half
+        rocblas_status st;
+        if (axis == 0)
+            st = gemm(g->blas, inverse ? T_ : N_, N_, m, n[1] * n[2], m, Sh, m, 0, A + off, n[0], 0, C + off, n[0], 0,
+                      1);
+        else if (axis == 1)
+            st = gemm(g->blas, N_, inverse ? N_ : T_, n[0], m, m, A + off * n[0], n[0], plane, Sh, m, 0,
+                      C + off * n[0], n[0], plane, n[2]);
+        else
+            st = gemm(g->blas, N_, inverse ? N_ : T_, (int)plane, m, m, A + off * plane, (int)plane, 0, Sh, m, 0,
+                      C + off * plane, (int)plane, 0, 1);
+        if (st != rocblas_status_success)
+            return fail(PPML_EHIP, "rocBLAS GEMM of the sine transform: status %d", (int)st);
+    }
     return PPML_OK;
 }
 
@@ -309,8 +323,9 @@ template <typename T> int launch_gravity(ppml_grid *g)
     T *phi = (T *)g->phi;
     T *X = (T *)g->wx;
     T *Y = (T *)g->wy;
+    const int rows = n1 * n2;
     const int nb = grav_blocks(N);
-    const long long chunk = (N + nb - 1) / nb;
+    const int chunk = (rows + nb - 1) / nb;
     k_grav_moments_partial<T><<<nb, GRAV_THREADS, 0, g->stream>>>(rho, gp, chunk, g->gpart);
     k_grav_moments_final<<<1, GRAV_THREADS, 0, g->stream>>>(g->gpart, nb, g->ctrl);
     const long long nshell = (long long)(n0 + 2) * (n1 + 2) * (n2 + 2) - N;
@@ -319,21 +334,22 @@ template <typename T> int launch_gravity(ppml_grid *g)
     k_grav_rhs<T><<<nbc, 256, 0, g->stream>>>(rho, gp, g->grav_coef, X);
     const long long nedge = grav_edge_cells(n0, n1, n2);
     k_grav_rhs_edge<T><<<(unsigned)((nedge + 255) / 256), 256, 0, g->stream>>>(rho, phi, gp, g->grav_coef, X);
+    const long long nrep = (long long)grav_no(n0) * grav_no(n1) * grav_no(n2);
+    const unsigned nbr = (unsigned)((nrep + 255) / 256);
+    k_grav_butterfly<T><<<nbr, 256, 0, g->stream>>>(X, Y, gp);
     HIPCHK(hipGetLastError());
     int rc;
-    if ((rc = sine_transform<T>(g, 0, X, Y))) return rc;
-    if ((rc = sine_transform<T>(g, 1, Y, X))) return rc;
-    if ((rc = sine_transform<T>(g, 2, X, Y))) return rc;
-    k_grav_eigdiv<T><<<nbc, 256, 0, g->stream>>>(Y, g->fx, g->fy, g->fz, gp, g->grav_norm);
+    if ((rc = sine_transform<T>(g, 0, false, Y, X))) return rc;
+    if ((rc = sine_transform<T>(g, 1, false, X, Y))) return rc;
+    if ((rc = sine_transform<T>(g, 2, false, Y, X))) return rc;
+    const dim3 ged((unsigned)((n0 + 255) / 256), (unsigned)std::min(rows, 32768));
+    k_grav_eigdiv<T><<<ged, 256, 0, g->stream>>>(X, g->fx, g->fy, g->fz, gp, g->grav_norm);
     HIPCHK(hipGetLastError());
-    if ((rc = sine_transform<T>(g, 2, Y, X))) return rc;
-    if ((rc = sine_transform<T>(g, 1, X, Y))) return rc;
-    // inverse x transform straight into the interior of the padded potential
-    const long long pplane = (long long)(n0 + 2) * (n1 + 2);
-    T *dst = phi + pplane + (n0 + 2) + 1;
-    rocblas_status st = gemm(g->blas, n0, n1, n0, (const T *)g->sx, n0, 0, Y, n0, (long long)n0 * n1, dst, n0 + 2,
-                             pplane, n2);
-    if (st != rocblas_status_success) return fail(PPML_EHIP, "rocBLAS GEMM of the sine transform: status %d", (int)st);
+    if ((rc = sine_transform<T>(g, 2, true, X, Y))) return rc;
+    if ((rc = sine_transform<T>(g, 1, true, Y, X))) return rc;
+    if ((rc = sine_transform<T>(g, 0, true, X, Y))) return rc;
+    k_grav_unbutterfly<T><<<nbr, 256, 0, g->stream>>>(Y, phi, gp);
+    HIPCHK(hipGetLastError());
     return PPML_OK;
 }
 
@@ -609,8 +625,7 @@ int ppml_create(const ppml_desc *d, void *state_dev, void *scratch_dev, void *hi
             delete g;
             return fail(PPML_EHIP, "rocblas_set_stream failed");
         }
-        const long long nt = (long long)gp.n[0] * gp.n[0] + (long long)gp.n[1] * gp.n[1] +
-                             (long long)gp.n[2] * gp.n[2] + gp.n[0] + gp.n[1] + gp.n[2];
+        const long long nt = grav_table_count(gp.n[0]) + grav_table_count(gp.n[1]) + grav_table_count(gp.n[2]);
         const unsigned nbt = (unsigned)((nt + 255) / 256);
         if (d->prec == PPML_FP64)
             k_grav_tables<double><<<nbt, 256, 0, g->stream>>>((double *)g->sx, (double *)g->sy, (double *)g->sz,

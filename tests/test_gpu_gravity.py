@@ -235,3 +235,28 @@ def test_timing_split_reports_the_gravity_solve():
     mg2, me2, ml2, n2 = g2.get_timing_split()
     # no gravity: the first interval holds no work, only the event overhead
     assert n2 == 2 and me2 > 0.0 and mg2 < 0.05 * n2 and mg2 < mg
+
+
+def test_galaxy_disk_configuration_vs_oracle():
+    """The paper's disk configuration (isothermal gas, self-gravity, fixed halo
+    potential; synthetic data) on a 40^3 mesh, 8 steps driven by the oracle's
+    time steps: FP64 within 1e-10 per field in both builds, FP32 within 1e-4
+    (L1, density)."""
+    prob = W.galaxy_disk(40, seed=2)
+    o = make_oracle(prob)
+    taus = o.run(8)
+    for exact in (True, False):
+        g = _grid(prob, exact=exact)
+        for tau in taus:
+            g.step(1, dt_fixed=float(tau))
+        for f in range(6):
+            err = _rel(g.get(f), o.get(f))
+            print(f"galaxy 40^3 exact={exact} field {f}: rel err {err:.3e}", flush=True)
+            assert err <= 1e-10, (exact, f, err)
+    g32 = _grid(prob, prec="fp32")
+    for tau in taus:
+        g32.step(1, dt_fixed=float(tau))
+    r64 = o.get("rho")
+    l1 = float(np.sum(np.abs(g32.get("rho") - r64)) / np.sum(r64))
+    print(f"galaxy 40^3 fp32: L1(rho) {l1:.3e}", flush=True)
+    assert l1 <= 1e-4
