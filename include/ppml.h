@@ -100,7 +100,8 @@ typedef struct {
                               the list of ppml_tile_shape (0 = default); changes
                               the speed only, never the results                  */
     int32_t self_gravity;  /* 1: add the force of the gas's own potential (Sec. 2.5,
-                              see below); 0: none.  Needs ndim = 3 and cubic cells */
+                              see below); 0: none.  Needs ndim = 3, cubic cells and
+                              the origin off the centres of the shell cells     */
     double inflow[6][5];   /* ghost state (rho, vx, vy, vz, p) of face 2*axis+side
                               (side 0 low, 1 high) where that face is PPML_INFLOW;
                               rho, p > 0; converted like ppml_set_primitive   */

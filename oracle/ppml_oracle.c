@@ -467,6 +467,14 @@ int og_set_self_gravity(og_grid *g, double G)
     if (g->ndim != 3) return -1;
     double h = g->h[0];
     if (fabs(g->h[1] - h) > 1e-12 * h || fabs(g->h[2] - h) > 1e-12 * h) return -1;
+    /* the expansion about the origin is undefined at the origin itself */
+    int on_grid = 1, on_shell = 0;
+    for (int a = 0; a < 3; a++) {
+        double u = (0.0 - g->lo[a]) / h - 0.5, ur = nearbyint(u);
+        if (fabs(u - ur) > 1e-9 || ur < -1.0 || ur > (double)g->n[a]) on_grid = 0;
+        if (ur == -1.0 || ur == (double)g->n[a]) on_shell = 1;
+    }
+    if (on_grid && on_shell) return -1;
     if (!g->phi) g->phi = (double *)calloc((size_t)((g->n[0] + 2) * (g->n[1] + 2) * (g->n[2] + 2)), sizeof(double));
     g->self_grav = 1;
     g->grav_G = G;

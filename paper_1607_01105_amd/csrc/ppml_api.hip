@@ -132,6 +132,15 @@ int validate(const ppml_desc *d)
             if (std::fabs(ha - h0) > 1e-12 * h0) return fail(PPML_EINVAL, "self-gravity needs cubic cells");
         }
         if (!(d->grav_G > 0.0) || !std::isfinite(d->grav_G)) return fail(PPML_EINVAL, "grav_G must be > 0");
+        // the multipole expansion about the origin is undefined at the origin
+        int on_grid = 1, on_shell = 0;
+        for (int a = 0; a < 3; a++) {
+            const double u = (0.0 - d->lo[a]) / h0 - 0.5;  // origin in cell units
+            const double ur = std::nearbyint(u);
+            if (std::fabs(u - ur) > 1e-9 || ur < -1.0 || ur > (double)d->n[a]) on_grid = 0;
+            if (ur == -1.0 || ur == (double)d->n[a]) on_shell = 1;
+        }
+        if (on_grid && on_shell) return fail(PPML_EINVAL, "the origin (the multipole centre) is a shell cell centre");
     }
     return PPML_OK;
 }

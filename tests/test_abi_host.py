@@ -141,6 +141,13 @@ def test_self_gravity_descriptor(lib):
                 dict(self_gravity=0.0, **cube), dict(self_gravity=-1.0, **cube),
                 dict(self_gravity=1.0, ndim=2, n=(16, 16), lo=(0, 0), hi=(1, 1))):
         assert ppml.ppml_state_bytes(_desc(**bad), lib) == 0, bad
+    # the origin on a shell cell centre: x = -h/2 is the centre of cell -1 when lo = 0
+    h = 1.0 / 16
+    assert ppml.ppml_state_bytes(_desc(self_gravity=1.0, n=(16, 8, 4), lo=(0.0, -0.25, -0.125),
+                                       hi=(1.0, 0.25, 0.125)), lib) > 0
+    lo = (h / 2, -4.5 * h, -2.5 * h)
+    hi = (lo[0] + 16 * h, lo[1] + 8 * h, lo[2] + 4 * h)
+    assert ppml.ppml_state_bytes(_desc(self_gravity=1.0, n=(16, 8, 4), lo=lo, hi=hi), lib) == 0
     d = _desc(**cube)
     d.self_gravity = 2
     d.grav_G = 1.0
