@@ -971,30 +971,79 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                 }
             }
             __syncthreads();
-            // interface values (Appendix step 1) at every face of the tile
-            for (int j = tid; j < NXQ + NYQ; j += NT) {
-                if (j < NXQ) {
-                    const int fxi = j % (TX + 3), cy = j / (TX + 3);
-                    const int l = (cy + HY) * PW + fxi;  // q of tile-rel cells fxi-3 .. fxi
+            // interface values (Appendix step 1) at every face of the tile.  In
+            // FP64, two neighbouring faces per job share the limited slope of
+            // the cell between them (3 slopes for 2 faces; the last job of a
+            // row or column may hold one face); the FP32 kernel, at its
+            // register limit, takes one face per job.
+            if constexpr (sizeof(T) == 8) {
+                constexpr int PXR = (TX + 4) / 2;             // x jobs per row
+                constexpr int PYC = (TY + 4) / 2;             // y jobs per column
+                constexpr int NPX = PXR * TY;
+                constexpr int NPY = NDIM >= 2 ? PYC * TX : 0;
+                for (int j = tid; j < NPX + NPY; j += NT) {
+                    if (j < NPX) {
+                        const int p = j % PXR, cy = j / PXR;
+                        const int fxi = 2 * p;                    // faces fxi, fxi + 1
+                        const bool two = fxi + 1 <= TX + 2;
+                        const int l = (cy + HY) * PW + fxi;       // q of tile-rel cells fxi-3 .. fxi+1
+                        const int o = cy * (TX + 3) + fxi;
 #pragma unroll
-                    for (int g = 0; g < G; g++) {
-                        if (f0 + g >= NF) break;
-                        const T *q = sf[g];
-                        const T da = limited_slope(q[l], q[l + 1], q[l + 2]);
-                        const T db = limited_slope(q[l + 1], q[l + 2], q[l + 3]);
-                        s_qx[g][j] = interface_value(q[l + 1], q[l + 2], da, db);
+                        for (int g = 0; g < G; g++) {
+                            if (f0 + g >= NF) break;
+                            const T *q = sf[g];
+                            const T da = limited_slope(q[l], q[l + 1], q[l + 2]);
+                            const T db = limited_slope(q[l + 1], q[l + 2], q[l + 3]);
+                            s_qx[g][o] = interface_value(q[l + 1], q[l + 2], da, db);
+                            if (two) {
+                                const T dc = limited_slope(q[l + 2], q[l + 3], q[l + 4]);
+                                s_qx[g][o + 1] = interface_value(q[l + 2], q[l + 3], db, dc);
+                            }
+                        }
+                    } else if constexpr (NDIM >= 2) {
+                        const int jj = j - NPX;
+                        const int cx = jj % TX, fyi = 2 * (jj / TX);  // faces fyi, fyi + 1
+                        const bool two = fyi + 1 <= TY + 2;
+                        const int l = fyi * PW + cx + HX;            // rows fyi-3 .. fyi+1 (tile-rel)
+#pragma unroll
+                        for (int g = 0; g < G; g++) {
+                            if (f0 + g >= NF) break;
+                            const T *q = sf[g];
+                            const T da = limited_slope(q[l], q[l + PW], q[l + 2 * PW]);
+                            const T db = limited_slope(q[l + PW], q[l + 2 * PW], q[l + 3 * PW]);
+                            s_qy[g][fyi * TX + cx] = interface_value(q[l + PW], q[l + 2 * PW], da, db);
+                            if (two) {
+                                const T dc = limited_slope(q[l + 2 * PW], q[l + 3 * PW], q[l + 4 * PW]);
+                                s_qy[g][(fyi + 1) * TX + cx] = interface_value(q[l + 2 * PW], q[l + 3 * PW], db, dc);
+                            }
+                        }
                     }
-                } else if constexpr (NDIM >= 2) {
-                    const int jj = j - NXQ;
-                    const int cx = jj % TX, fyi = jj / TX;
-                    const int l = fyi * PW + cx + HX;  // rows fyi-3 .. fyi (tile-rel)
+                }
+            } else {
+                for (int j = tid; j < NXQ + NYQ; j += NT) {
+                    if (j < NXQ) {
+                        const int fxi = j % (TX + 3), cy = j / (TX + 3);
+                        const int l = (cy + HY) * PW + fxi;  // q of tile-rel cells fxi-3 .. fxi
 #pragma unroll
-                    for (int g = 0; g < G; g++) {
-                        if (f0 + g >= NF) break;
-                        const T *q = sf[g];
-                        const T da = limited_slope(q[l], q[l + PW], q[l + 2 * PW]);
-                        const T db = limited_slope(q[l + PW], q[l + 2 * PW], q[l + 3 * PW]);
-                        s_qy[g][jj] = interface_value(q[l + PW], q[l + 2 * PW], da, db);
+                        for (int g = 0; g < G; g++) {
+                            if (f0 + g >= NF) break;
+                            const T *q = sf[g];
+                            const T da = limited_slope(q[l], q[l + 1], q[l + 2]);
+                            const T db = limited_slope(q[l + 1], q[l + 2], q[l + 3]);
+                            s_qx[g][j] = interface_value(q[l + 1], q[l + 2], da, db);
+                        }
+                    } else if constexpr (NDIM >= 2) {
+                        const int jj = j - NXQ;
+                        const int cx = jj % TX, fyi = jj / TX;
+                        const int l = fyi * PW + cx + HX;  // rows fyi-3 .. fyi (tile-rel)
+#pragma unroll
+                        for (int g = 0; g < G; g++) {
+                            if (f0 + g >= NF) break;
+                            const T *q = sf[g];
+                            const T da = limited_slope(q[l], q[l + PW], q[l + 2 * PW]);
+                            const T db = limited_slope(q[l + PW], q[l + 2 * PW], q[l + 3 * PW]);
+                            s_qy[g][jj] = interface_value(q[l + PW], q[l + 2 * PW], da, db);
+                        }
                     }
                 }
             }
