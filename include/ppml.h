@@ -12,7 +12,9 @@
  * (acoustic Riemann problem on parabolas, pressure and force terms, no
  * advection; Sec. 2.1-2.2) + Lagrangian stage (upwind parabolic advection
  * with the 9-point transverse velocity; Sec. 2.3) + total-energy correction
- * (Sec. 2.4).  Every step runs in HIP kernels on the caller's stream.
+ * (Sec. 2.4), optionally preceded by the self-gravity potential solve
+ * (Sec. 2.5).  Every step runs in HIP kernels on the caller's stream (the
+ * self-gravity transforms as rocBLAS GEMMs on the same stream).
  *
  * Conventions shared by every function:
  *  - Return value: PPML_OK (0) or a negative ppml_status.  Nothing throws
@@ -118,8 +120,9 @@ typedef struct {
  * expansion about the coordinate origin (monopole and quadrupole; the
  * quadrupole with MacCullagh's factor 1/2) and moved to the right-hand side;
  * the Dirichlet problem is solved exactly by sine transforms along each axis
- * (products with the N x N sine matrices on the matrix cores), division by
- * the stencil's eigenvalues and the inverse transforms.  The force terms of
+ * (sums and differences of mirror cells, then products with the half-size
+ * odd- and even-mode sine matrices on the matrix cores), division by the
+ * stencil's eigenvalues and the inverse transforms.  The force terms of
  * eqs. (2)-(3) then use the central difference of the potential across each
  * cell, added to any fixed potential's gradient.  The scratch area grows by
  * the potential, two work arrays of the grid's size and the sine tables
