@@ -57,10 +57,11 @@ KERNEL_SOURCES = ("paper_1607_01105_amd/csrc/ppml_kernels.hpp", "paper_1607_0110
                   "paper_1607_01105_amd/build.py")
 
 
-def measured_traffic(kernel_key: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary
-    (FETCH_SIZE and WRITE_SIZE scaled by the calibration kernel), or None when
-    the kernel sources changed since the counters were taken."""
+def measured_counters(kernel_key: str):
+    """The committed rocprofv3 counter summary of one kernel: HBM bytes per
+    launch (FETCH_SIZE and WRITE_SIZE scaled by the calibration kernel) and
+    VALU lane-instructions per zone (SQ_INSTS_VALU x 64 / zones), or None
+    when the kernel sources changed since the counters were taken."""
     import hashlib
 
     try:
@@ -72,7 +73,16 @@ def measured_traffic(kernel_key: str):
         h.update(open(os.path.join(ROOT, s), "rb").read())
     if tr.get("source_sha256") != h.hexdigest() or kernel_key not in tr:
         return None
-    return tr[kernel_key]["bytes"]
+    return tr[kernel_key]
+
+
+def measured_traffic(kernel_key: str):
+    c = measured_counters(kernel_key)
+    return None if c is None else c["bytes"]
+
+
+# VALU issue roof: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 lane-instructions/s
+VALU_ISSUE_PEAK = 256 * 64 * 2.4e9
 
 
 def algorithmic_bytes_per_zone(kernel: str, ndim: int, width: int) -> int:
@@ -253,7 +263,13 @@ def run_riemann_1d(seeds=range(16)):
     from paper_1607_01105_amd import workloads as W
     from paper_1607_01105_amd.ppml import Grid
 
+    import numpy as np
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import exact_riemann as er  # the exact solution, written from the mathematics
+
     zu, sec = 0, 0.0
+    l1, l1x = [], []
     for s in seeds:
         prob = W.riemann_1d(s)
         g = Grid.from_problem(prob, prec="fp64")
@@ -262,10 +278,22 @@ def run_riemann_1d(seeds=range(16)):
         _, _, n = g.run_to(prob.t_stop)
         sec += time.perf_counter() - t0
         zu += prob.cells * n
+        left, right = W.riemann_states(s)
+        ex = er.cell_averages(left, right, prob.gamma, 0.5, prob.t_stop, np.linspace(0.0, 1.0, 513), sub=8)
+        l1.append(float(np.mean(np.abs(g.get("rho").ravel() - ex[0]))))
         del g
+        # waves can reach x = 0 or 1 by t = 0.15: the same problem on [-1, 2]
+        # (1536 cells), compared on [0, 1], leaves the outflow faces out
+        big = W.riemann_1d(s, n=1536, lo=-1.0, hi=2.0)
+        gb = Grid.from_problem(big, prec="fp64")
+        gb.run_to(big.t_stop)
+        l1x.append(float(np.mean(np.abs(gb.get("rho").ravel()[512:1024] - ex[0]))))
+        del gb
     torch.cuda.empty_cache()
     return {"workload": "1-D Riemann, 512 cells, FP64, seeds 0-15, t = 0.15 (host-driven chunks of 64 steps)",
-            "zone_updates_per_s": zu / sec, "zone_updates": zu, "seconds": sec}
+            "zone_updates_per_s": zu / sec, "zone_updates": zu, "seconds": sec,
+            "l1_rho_vs_exact": {"mean": float(np.mean(l1)), "max": float(np.max(l1))},
+            "l1_rho_vs_exact_extended_domain": {"mean": float(np.mean(l1x)), "max": float(np.max(l1x))}}
 
 
 def run_suite():
@@ -434,7 +462,16 @@ def cpu_baseline(prob, min_seconds=10.0, max_steps=30):
         steps1 += 1
     oracle.set_threads(cores)
     del o
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": prob.cells * steps / sec, "unit": "zone-updates/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model, "nproc": os.cpu_count(),
             "sample": f"first {steps} steps of the same 256^3 workload ({prob.cells * steps} zone-updates), "
                       f"FP64, {sec:.1f} s of stepping on {cores} threads; then {steps1} more step(s) on 1 thread",
             "one_core_value": prob.cells * steps1 / sec1}
@@ -451,7 +488,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched and served runs")
     ap.add_argument("--serve-requests", type=int, default=60)
     ap.add_argument("--no-tune", action="store_true", help="use the default tile shape instead of the autotuner's")
-    ap.add_argument("--leg", choices=["gravity", "galaxy", "disk", "disk_isothermal", "suite", "batched"], default=None,
+    ap.add_argument("--leg", choices=["gravity", "galaxy", "disk", "disk_isothermal", "suite", "batched", "riemann_1d"],
+                    default=None,
                     help="run only this configuration (its JSON object, no headline line); for profiling")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one plain 256 MiB streaming kernel (torch.mul out-of-place: reads 256 MiB, "
@@ -478,7 +516,8 @@ def main():
     if args.leg is not None:
         legs = {"gravity": lambda: run_gravity(steps=args.steps), "disk": lambda: run_disk(steps=args.steps),
                 "disk_isothermal": lambda: run_disk(steps=args.steps, isothermal=True), "suite": run_suite,
-                "batched": lambda: run_batched(steps=args.steps), "galaxy": lambda: run_galaxy(steps=args.steps)}
+                "batched": lambda: run_batched(steps=args.steps), "galaxy": lambda: run_galaxy(steps=args.steps),
+                "riemann_1d": run_riemann_1d}
         print(json.dumps({args.leg: legs[args.leg]()}))
         return
     prob = W.periodic_modes(args.n, seed=0)
@@ -521,6 +560,15 @@ def main():
     key = f"k_{kern}<{'float' if width == 4 else 'double'},3,{tx},{ty}" + (
         f",{6 if width == 4 else 3}>" if kern == "lagr" else ">")
     traffic = measured_traffic(key)
+    cnt = measured_counters(key)
+    valu_issue = None
+    if cnt and "valu_lane_instr_per_zone" in cnt:
+        # every lane-instruction the kernel issues (address arithmetic,
+        # selects and moves included) against the VALU issue rate
+        ach = cnt["valu_lane_instr_per_zone"] * cells / (ms_k * 1e-3)
+        valu_issue = {"lane_instr_per_zone": cnt["valu_lane_instr_per_zone"], "achieved": ach,
+                      "peak": VALU_ISSUE_PEAK, "unit": "lane-instr/s", "frac": ach / VALU_ISSUE_PEAK,
+                      "valu_busy_pct": cnt.get("valu_busy_pct")}
     out = {
         "metric": "zone-updates/sec FP32 vs FP64 at stated L1 error; p50/p99 latency when served",
         "value": value,
@@ -543,6 +591,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": "k_" + kern, "achieved": achieved_tflops,
                      "peak": VALU_PEAK_TFLOPS[dt], "unit": "TFLOP/s", "frac": achieved_tflops / VALU_PEAK_TFLOPS[dt],
                      "traffic": traffic, "algorithmic_flop_per_zone": ALGO_FLOP_PER_ZONE_3D[kern],
+                     "valu_issue": valu_issue,
                      "launch_ms": ms_k, "published_peak": FP32_VECTOR_PEAK_TFLOPS if dt == "f32" else FP64_VECTOR_PEAK_TFLOPS,
                      "hbm": {"achieved_GBs": achieved_gbs, "peak_GBs": HBM_PEAK_GBS,
                              "frac": achieved_gbs / HBM_PEAK_GBS,

@@ -155,3 +155,43 @@ def test_isothermal_tiles_and_batch():
         solo.step(6)
         for f in _fields(p.ndim):
             assert np.array_equal(b.grids[s].get(f), solo.get(f)), (p.name, f)
+
+
+def _combined():
+    iso_in = W.inflow_channel(2, (41, 27), seed=61)
+    iso_in = _iso(iso_in, 1.2)
+    iso_in.inflow = {0: (1.4, 3.0, 0.2, 0.0, 1.2 * 1.2 * 1.4)}
+    iso_fo = _iso(W.blocks(3, (21, 17, 15), seed=62, bc="outflow"), 0.8)
+    g_ref = W.gravity_sphere((26, 22, 18), noise=0.2, seed=63)
+    g_ref.bc = [("reflect", "reflect")] * 3
+    g_ref.name += "_reflect"
+    g_iso = W.gravity_sphere((24, 24, 20), noise=0.2, seed=64)
+    g_iso.isothermal = 0.3
+    g_iso.p = 0.09 * g_iso.rho
+    g_iso.name += "_iso"
+    return [("iso_inflow2d", iso_in, False), ("iso_first_order3d", iso_fo, True),
+            ("gravity_reflect3d", g_ref, False), ("gravity_iso3d", g_iso, False)]
+
+
+COMBINED = _combined()
+
+
+@pytest.mark.parametrize("name,prob,fo", COMBINED, ids=[c[0] for c in COMBINED])
+def test_combined_features(name, prob, fo):
+    """Features together: the isothermal variant with inflow faces and with
+    the first-order scheme (exact build, bit for bit), self-gravity with
+    reflecting walls and with the isothermal variant (FP64 within 1e-10 in
+    both builds; the transforms sum in another order than the oracle)."""
+    o = make_oracle(prob, first_order=fo)
+    taus = o.run(8)
+    grav = getattr(prob, "self_gravity", None) is not None
+    for exact in (True, False):
+        g = _grid(prob, exact=exact, first_order=fo)
+        for tau in taus:
+            g.step(1, dt_fixed=float(tau))
+        for f in _fields(prob.ndim):
+            a, b = g.get(f), o.get(f)
+            if exact and not grav:
+                assert np.array_equal(a, b), (name, f)
+            else:
+                assert _rel(a, b) <= (1e-10 if grav else 1e-12), (name, exact, f, _rel(a, b))
