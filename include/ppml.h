@@ -249,7 +249,8 @@ int ppml_batch_create(int32_t capacity, size_t budget_bytes, void *hip_stream, p
 
 /* Admit a grid whose state is set; *slot receives its slot.  While admitted
  * the grid is stepped only by the batch (ppml_step returns PPML_ESTATE); its
- * get/set/totals calls still work.  Errors: PPML_EBUDGET (budget or capacity
+ * get/set/totals/time/sync calls still work and, when the grid has a stream
+ * of its own, first wait for the batch stream's queued work.  Errors: PPML_EBUDGET (budget or capacity
  * exhausted), PPML_ESTATE (already in a batch, state not set), PPML_EINVAL
  * (other device or precision). */
 int ppml_batch_admit(ppml_batch *b, ppml_grid *g, int32_t *slot);

@@ -216,6 +216,7 @@ struct ppml_grid {
     double *partial;
     double *totals;
     bool in_batch;         // admitted to a batch: stepped only by the batch
+    hipStream_t bstream;   // that batch's stream (the batch kernels write the state there)
     bool has_state;
     std::vector<hipEvent_t> ev;  // 4 events per timed step
     long long timed;             // steps recorded since the last read
@@ -401,6 +402,14 @@ int check_err(ppml_grid *g)
 int grid_ok(ppml_grid *g)
 {
     if (!g) return fail(PPML_EINVAL, "grid is NULL");
+    return PPML_OK;
+}
+
+// A grid in a batch is stepped on the batch's stream: calls that touch its
+// state on the grid's own stream first wait for the batch's queued work.
+int settle(ppml_grid *g)
+{
+    if (g->in_batch && g->bstream != g->stream) HIPCHK(hipStreamSynchronize(g->bstream));
     return PPML_OK;
 }
 
@@ -675,6 +684,7 @@ int ppml_set_primitive(ppml_grid *g, const double *rho, const double *vx, const 
 {
     int rc = grid_ok(g);
     if (rc) return rc;
+    if ((rc = settle(g))) return rc;
     if (!rho || !p) return fail(PPML_EINVAL, "rho and p are required");
     const long long N = g->gp.ncell;
     if (!all_finite_positive(rho, N)) return fail(PPML_EINVAL, "rho must be finite and > 0");
@@ -683,20 +693,20 @@ int ppml_set_primitive(ppml_grid *g, const double *rho, const double *vx, const 
     for (int a = 0; a < g->d.ndim; a++)
         if (v[a] && !all_finite(v[a], N)) return fail(PPML_EINVAL, "velocity %d has non-finite values", a);
     double *prim = nullptr;
-    HIPCHK(hipMalloc(&prim, (size_t)5 * N * sizeof(double)));
+    HIPCHK(hipMallocAsync((void **)&prim, (size_t)5 * N * sizeof(double), g->stream));
     const double *src[5] = {rho, vx, vy, vz, p};
     for (int i = 0; i < 5; i++) {
         if (src[i]) {
             hipError_t e = hipMemcpyAsync(prim + (size_t)i * N, src[i], N * sizeof(double), hipMemcpyHostToDevice,
                                           g->stream);
             if (e != hipSuccess) {
-                (void)hipFree(prim);
+                (void)hipFreeAsync(prim, g->stream);
                 return fail(PPML_EHIP, "copy of primitive %d: %s", i, hipGetErrorString(e));
             }
         } else {
             hipError_t e = hipMemsetAsync(prim + (size_t)i * N, 0, N * sizeof(double), g->stream);
             if (e != hipSuccess) {
-                (void)hipFree(prim);
+                (void)hipFreeAsync(prim, g->stream);
                 return fail(PPML_EHIP, "hipMemsetAsync: %s", hipGetErrorString(e));
             }
         }
@@ -705,8 +715,8 @@ int ppml_set_primitive(ppml_grid *g, const double *rho, const double *vx, const 
     if (g->d.prec == PPML_FP64) k_prim_to_cons<double><<<nb, 256, 0, g->stream>>>(prim, (double *)g->state, g->gp);
     else k_prim_to_cons<float><<<nb, 256, 0, g->stream>>>(prim, (float *)g->state, g->gp);
     hipError_t e = hipGetLastError();
+    (void)hipFreeAsync(prim, g->stream);
     hipError_t e2 = hipStreamSynchronize(g->stream);
-    (void)hipFree(prim);
     if (e != hipSuccess || e2 != hipSuccess)
         return fail(PPML_EHIP, "prim_to_cons: %s", hipGetErrorString(e != hipSuccess ? e : e2));
     return finish_set(g, 0.0, 0.0);
@@ -716,6 +726,7 @@ int ppml_set_conserved(ppml_grid *g, const double *const *f, double rho_mean0, d
 {
     int rc = grid_ok(g);
     if (rc) return rc;
+    if ((rc = settle(g))) return rc;
     if (!f || !f[PPML_RHO] || !f[PPML_ETOT] || !f[PPML_EINT]) return fail(PPML_EINVAL, "rho, Et and e are required");
     const long long N = g->gp.ncell;
     const int nd = g->d.ndim;
@@ -724,7 +735,7 @@ int ppml_set_conserved(ppml_grid *g, const double *const *f, double rho_mean0, d
     if (!all_finite(f[PPML_ETOT], N)) return fail(PPML_EINVAL, "rho*E must be finite");
     if (!std::isfinite(t) || t < 0.0) return fail(PPML_EINVAL, "t must be finite and >= 0");
     double *tmp = nullptr;
-    HIPCHK(hipMalloc(&tmp, (size_t)N * sizeof(double)));
+    HIPCHK(hipMallocAsync((void **)&tmp, (size_t)N * sizeof(double), g->stream));
     int nb = (int)std::min<long long>(4096, (N + 255) / 256);
     // stored field s <- ppml_field
     int nfs = nfields(&g->d);
@@ -733,7 +744,7 @@ int ppml_set_conserved(ppml_grid *g, const double *const *f, double rho_mean0, d
         hipError_t e;
         if (f[fld]) {
             if (!all_finite(f[fld], N)) {
-                (void)hipFree(tmp);
+                (void)hipFreeAsync(tmp, g->stream);
                 return fail(PPML_EINVAL, "field %d has non-finite values", fld);
             }
             e = hipMemcpyAsync(tmp, f[fld], N * sizeof(double), hipMemcpyHostToDevice, g->stream);
@@ -749,11 +760,11 @@ int ppml_set_conserved(ppml_grid *g, const double *const *f, double rho_mean0, d
         }
         if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
         if (e != hipSuccess) {
-            (void)hipFree(tmp);
+            (void)hipFreeAsync(tmp, g->stream);
             return fail(PPML_EHIP, "set_conserved: %s", hipGetErrorString(e));
         }
     }
-    (void)hipFree(tmp);
+    (void)hipFreeAsync(tmp, g->stream);
     return finish_set(g, t, rho_mean0);
 }
 
@@ -782,6 +793,7 @@ int ppml_get_time(ppml_grid *g, double *t, double *dt_last, int64_t *steps)
 {
     int rc = grid_ok(g);
     if (rc) return rc;
+    if ((rc = settle(g))) return rc;
     Ctrl c;
     HIPCHK(hipMemcpyAsync(&c, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, g->stream));
     HIPCHK(hipStreamSynchronize(g->stream));
@@ -796,6 +808,7 @@ int ppml_max_speeds(ppml_grid *g, double *vmax, double *cmax)
 {
     int rc = grid_ok(g);
     if (rc) return rc;
+    if ((rc = settle(g))) return rc;
     Ctrl c;
     HIPCHK(hipMemcpyAsync(&c, g->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, g->stream));
     HIPCHK(hipStreamSynchronize(g->stream));
@@ -813,6 +826,7 @@ int ppml_get_conserved(ppml_grid *g, int32_t field, double *host_out)
 {
     int rc = grid_ok(g);
     if (rc) return rc;
+    if ((rc = settle(g))) return rc;
     if (!host_out) return fail(PPML_EINVAL, "host_out is NULL");
     const int nd = g->d.ndim;
     int s;
@@ -828,7 +842,7 @@ int ppml_get_conserved(ppml_grid *g, int32_t field, double *host_out)
     if (s < 0) return fail(PPML_EINVAL, "field %d is not stored for ndim=%d", field, nd);
     const long long N = g->gp.ncell;
     double *tmp = nullptr;
-    HIPCHK(hipMalloc(&tmp, (size_t)N * sizeof(double)));
+    HIPCHK(hipMallocAsync((void **)&tmp, (size_t)N * sizeof(double), g->stream));
     int nb = (int)std::min<long long>(4096, (N + 255) / 256);
     if (g->d.prec == PPML_FP64)
         k_to_double<double><<<nb, 256, 0, g->stream>>>((const double *)g->state + (size_t)s * N, tmp, N);
@@ -837,7 +851,7 @@ int ppml_get_conserved(ppml_grid *g, int32_t field, double *host_out)
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(host_out, tmp, N * sizeof(double), hipMemcpyDeviceToHost, g->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-    (void)hipFree(tmp);
+    (void)hipFreeAsync(tmp, g->stream);
     if (e != hipSuccess) return fail(PPML_EHIP, "get_conserved: %s", hipGetErrorString(e));
     return PPML_OK;
 }
@@ -846,6 +860,7 @@ int ppml_totals(ppml_grid *g, double out[6])
 {
     int rc = grid_ok(g);
     if (rc) return rc;
+    if ((rc = settle(g))) return rc;
     if (!out) return fail(PPML_EINVAL, "out is NULL");
     if (!g->has_state) return fail(PPML_ESTATE, "state was never set");
     if (g->d.prec == PPML_FP64) launch_totals<double>(g, 0.0);
@@ -860,6 +875,7 @@ int ppml_sync(ppml_grid *g)
 {
     int rc = grid_ok(g);
     if (rc) return rc;
+    if ((rc = settle(g))) return rc;
     return check_err(g);
 }
 
@@ -921,14 +937,14 @@ int ppml_get_potential(ppml_grid *g, double *host_out)
     if (rc) return rc;
     const long long np = (long long)(g->gp.n[0] + 2) * (g->gp.n[1] + 2) * (g->gp.n[2] + 2);
     double *tmp = nullptr;
-    HIPCHK(hipMalloc(&tmp, (size_t)np * sizeof(double)));
+    HIPCHK(hipMallocAsync((void **)&tmp, (size_t)np * sizeof(double), g->stream));
     int nb = (int)std::min<long long>(4096, (np + 255) / 256);
     if (g->d.prec == PPML_FP64) k_to_double<double><<<nb, 256, 0, g->stream>>>((const double *)g->phi, tmp, np);
     else k_to_double<float><<<nb, 256, 0, g->stream>>>((const float *)g->phi, tmp, np);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(host_out, tmp, np * sizeof(double), hipMemcpyDeviceToHost, g->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-    (void)hipFree(tmp);
+    (void)hipFreeAsync(tmp, g->stream);
     if (e != hipSuccess) return fail(PPML_EHIP, "get_potential: %s", hipGetErrorString(e));
     return PPML_OK;
 }
@@ -1146,6 +1162,7 @@ int ppml_batch_admit(ppml_batch *b, ppml_grid *g, int32_t *slot)
     b->in_use += need;
     b->prec = g->d.prec;
     g->in_batch = true;
+    g->bstream = b->stream;
     b->dirty = true;
     if (slot) *slot = s;
     return PPML_OK;

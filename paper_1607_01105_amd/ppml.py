@@ -350,10 +350,19 @@ class Batch:
             self.lib.ppml_batch_destroy(h)
             self.h = None
 
-    def new_grid(self, prob, prec="fp32", vacuum_ratio=1e-5):
-        """A grid for this batch (same stream and library), state set."""
+    def new_grid(self, prob, prec="fp32", vacuum_ratio=1e-5, stream=None):
+        """A grid for this batch (same library), state set; on the batch's
+        stream unless another is given (its state transfer then overlaps the
+        batch's kernels)."""
         return Grid.from_problem(prob, prec=prec, exact=self.exact, vacuum_ratio=vacuum_ratio, device=self.device,
-                                 stream=self.stream)
+                                 stream=stream or self.stream)
+
+    def side_stream(self):
+        """A second stream on the batch's device, for preparing grids while the
+        batch steps."""
+        import torch
+
+        return torch.cuda.Stream(self.device)
 
     def admit(self, grid) -> int:
         s = C.c_int32()

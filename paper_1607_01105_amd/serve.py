@@ -2,14 +2,18 @@
 
 Requests of a served trace arrive on a Poisson clock.  Each scheduler round
 
-1. admits arrived requests, oldest first, while the memory budget (state +
-   scratch of the admitted grids) and the batch capacity allow: the request's
-   initial state is copied to its device buffers and the grid joins the batch;
-2. advances every admitted grid by min(its remaining steps, round_steps) in
-   one batched launch sequence (every grid keeps its own CFL time step);
-3. retires grids whose steps are done: the final state is copied to the
-   host and the completion latency (arrival -> final state on the host) is
-   recorded; their memory is released for the next admissions.
+1. admits the grids prepared during the previous round into the batch;
+2. enqueues the advance of every admitted grid by min(its remaining steps,
+   round_steps) in one batched launch sequence (every grid keeps its own CFL
+   time step);
+3. while the GPU runs that round, prepares arrived requests, oldest first,
+   while the memory budget (state + scratch of the admitted and prepared
+   grids) and the batch capacity allow: the request's initial state is
+   copied to new device buffers on a second stream, so the copies and the
+   state conversion overlap the batch's kernels;
+4. waits for the round and retires grids whose steps are done: the final
+   state is copied to the host and the completion latency (arrival -> final
+   state on the host) is recorded; their memory is released.
 
 Requests that arrive while others are on the GPU join at the next round
 boundary, so new work overlaps the running work on the device.  The
@@ -79,6 +83,7 @@ class Server:
     def run(self, trace, time_scale: float = 1.0, log=None) -> dict:
         """Serve the requests of `trace` (workloads.served_trace) in real time;
         arrival times are multiplied by time_scale."""
+        side = self.batch.side_stream()  # admissions are prepared here
         reqs = sorted(trace, key=lambda r: r.arrival)
         for r in reqs:
             if self._grid_bytes(r) > self.budget:
@@ -88,6 +93,7 @@ class Server:
         nxt = 0  # next request whose data are not yet submitted
         pending = collections.deque(reqs)
         waiting: collections.deque = collections.deque()
+        prepared: collections.deque = collections.deque()  # (request, grid, bytes, data wait)
         active: dict[int, list] = {}
         done: list[Completed] = []
         in_use = 0
@@ -103,34 +109,48 @@ class Server:
                 futures[r.rid] = pool.submit(r.problem)
                 nxt += 1
 
-        try:
-            while pending or waiting or active:
+        def arrivals():
+            now = clock()
+            while pending and pending[0].arrival * time_scale <= now:
+                waiting.append(pending.popleft())
+
+        def prepare():
+            # FIFO while budget and capacity allow: state set on the side
+            # stream (the call returns once the state is on the device)
+            nonlocal in_use
+            while waiting and len(active) + len(prepared) < self.capacity:
+                r = waiting[0]
+                need = self._grid_bytes(r)
+                if in_use + need > self.budget:
+                    break
+                t_req = clock()
+                fut = futures.pop(r.rid, None)
+                prob = fut.result() if fut is not None else r.problem()
+                data_wait = max(0.0, clock() - max(t_req, r.arrival * time_scale))
+                g = self.batch.new_grid(prob, prec=self.prec, stream=side)
+                in_use += need
+                prepared.append((r, g, need, data_wait))
+                waiting.popleft()
                 prefetch()
-                now = clock()
-                while pending and pending[0].arrival * time_scale <= now:
-                    waiting.append(pending.popleft())
-                # admission: FIFO while budget and capacity allow
-                while waiting and len(active) < self.capacity:
-                    r = waiting[0]
-                    need = self._grid_bytes(r)
-                    if in_use + need > self.budget:
-                        break
-                    t_req = clock()
-                    fut = futures.pop(r.rid, None)
-                    prob = fut.result() if fut is not None else r.problem()
-                    data_wait = max(0.0, clock() - max(t_req, r.arrival * time_scale))
-                    g = self.batch.new_grid(prob, prec=self.prec)
+
+        try:
+            while pending or waiting or prepared or active:
+                prefetch()
+                arrivals()
+                while prepared:
+                    r, g, need, data_wait = prepared.popleft()
                     slot = self.batch.admit(g)
-                    in_use += need
                     active[slot] = [r, g, r.steps, clock(), data_wait, need]
-                    waiting.popleft()
-                    prefetch()
                 if not active:
-                    if pending:
+                    prepare()
+                    if not prepared and pending:
                         time.sleep(max(0.0, min(pending[0].arrival * time_scale - clock(), 0.05)))
                     continue
                 steps = {s: min(a[2], self.round_steps) for s, a in active.items()}
                 self.batch.step(max(steps.values()), steps, graph=self.graph)
+                # the round runs on the GPU meanwhile
+                arrivals()
+                prepare()
                 self.batch.sync()
                 rounds += 1
                 for s in list(active):

@@ -132,3 +132,27 @@ def test_admission_budget_capacity_and_states():
     with pytest.raises(ppml.PPMLError) as e:
         c.step(3, {0: 5})
     assert e.value.status == ppml.PPML_EINVAL
+
+
+def test_reads_of_batched_grid_on_its_own_stream_wait_for_the_batch():
+    """A grid created on a stream of its own and stepped by a batch on
+    another stream: its read-back calls, issued right after the batch's
+    launches with no explicit synchronisation, wait for the batch's work and
+    return the stepped state (the bits of the same grid stepped alone)."""
+    import torch
+
+    from paper_1607_01105_amd.ppml import Batch, Grid
+
+    prob = W.blocks(3, (64, 48, 40), seed=71)
+    own = torch.cuda.Stream()
+    g = Grid.from_problem(prob, prec="fp32", stream=own)
+    b = Batch(capacity=2, stream=torch.cuda.Stream())
+    b.admit(g)
+    b.step(30, graph=False)
+    got = [g.get(f) for f in _fields(3)]       # no b.sync() before the reads
+    t = g.time()
+    solo = Grid.from_problem(prob, prec="fp32")
+    solo.step(30)
+    for f, a in zip(_fields(3), got):
+        assert np.array_equal(a, solo.get(f)), f
+    assert t[2] == 30

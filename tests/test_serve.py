@@ -28,8 +28,11 @@ class _FakeBatch:
         self.capacity, self.budget, self.lib = capacity, budget, lib
         self.grids, self.order, self.max_in_use, self.in_use = {}, [], 0, 0
 
-    def new_grid(self, prob, prec="fp32"):
+    def new_grid(self, prob, prec="fp32", stream=None):
         return _FakeGrid(prob)
+
+    def side_stream(self):
+        return None
 
     def _bytes(self, g):
         from paper_1607_01105_amd.ppml import make_desc, ppml_scratch_bytes, ppml_state_bytes
