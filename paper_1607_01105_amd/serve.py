@@ -11,9 +11,10 @@ Requests of a served trace arrive on a Poisson clock.  Each scheduler round
    grids) and the batch capacity allow: the request's initial state is
    copied to new device buffers on a second stream, so the copies and the
    state conversion overlap the batch's kernels;
-4. waits for the round and retires grids whose steps are done: the final
-   state is copied to the host and the completion latency (arrival -> final
-   state on the host) is recorded; their memory is released.
+4. waits for the round and retires grids whose steps are done; their final
+   states are copied to the host while the next round runs (before that
+   round's admissions are prepared), the completion latency (arrival -> final
+   state on the host) is recorded and their memory is released.
 
 Requests that arrive while others are on the GPU join at the next round
 boundary, so new work overlaps the running work on the device.  The
@@ -133,8 +134,30 @@ class Server:
                 waiting.popleft()
                 prefetch()
 
+        finished: list = []  # retired grids whose final state is still on the device
+
+        def read_back():
+            # final states of the retired grids (on their own streams, so the
+            # copies overlap a round that is already running); their memory
+            # returns to the budget afterwards
+            nonlocal in_use, zu_done
+            for a in finished:
+                r, g = a[0], a[1]
+                rho = g.get("rho")
+                t_done = clock()
+                if self.keep_results:
+                    self.results[r.rid] = rho
+                done.append(Completed(r.rid, r.ndim, r.n, r.steps, r.arrival * time_scale, a[3], t_done, a[4],
+                                      float(np.sum(rho))))
+                zu_done += r.cells * r.steps
+                in_use -= a[5]
+                if log:
+                    log(f"[serve] done rid={r.rid} {r.ndim}d n={r.n} steps={r.steps} "
+                        f"latency={t_done - r.arrival * time_scale:.3f}s active={len(active)}")
+            finished.clear()
+
         try:
-            while pending or waiting or prepared or active:
+            while pending or waiting or prepared or active or finished:
                 prefetch()
                 arrivals()
                 while prepared:
@@ -142,13 +165,16 @@ class Server:
                     slot = self.batch.admit(g)
                     active[slot] = [r, g, r.steps, clock(), data_wait, need]
                 if not active:
+                    read_back()
                     prepare()
                     if not prepared and pending:
                         time.sleep(max(0.0, min(pending[0].arrival * time_scale - clock(), 0.05)))
                     continue
                 steps = {s: min(a[2], self.round_steps) for s, a in active.items()}
                 self.batch.step(max(steps.values()), steps, graph=self.graph)
-                # the round runs on the GPU meanwhile
+                # the round runs on the GPU meanwhile: results of the previous
+                # round, then the next admissions
+                read_back()
                 arrivals()
                 prepare()
                 self.batch.sync()
@@ -158,20 +184,9 @@ class Server:
                     a[2] -= steps[s]
                     if a[2] > 0:
                         continue
-                    r, g = a[0], a[1]
                     self.batch.retire(s)
-                    rho = g.get("rho")
-                    t_done = clock()
-                    if self.keep_results:
-                        self.results[r.rid] = rho
-                    done.append(Completed(r.rid, r.ndim, r.n, r.steps, r.arrival * time_scale, a[3], t_done, a[4],
-                                          float(np.sum(rho))))
-                    zu_done += r.cells * r.steps
-                    in_use -= a[5]
+                    finished.append(a)
                     del active[s]
-                    if log:
-                        log(f"[serve] done rid={r.rid} {r.ndim}d n={r.n} steps={r.steps} "
-                            f"latency={t_done - r.arrival * time_scale:.3f}s active={len(active)}")
         finally:
             pool.shutdown(wait=True)
         t_end = clock()
