@@ -69,8 +69,14 @@ typedef enum { PPML_RHO = 0, PPML_MX = 1, PPML_MY = 2, PPML_MZ = 3, PPML_ETOT = 
  * equations (eqs. (2)-(3)):
  *   PPML_POT_LOG:     Phi = v0^2/2 ln(rc^2 + X^2 + Y^2 + Z^2/q^2), X = x - cx, ...
  *                     pot = {v0, rc, q, cx, cy, cz}
- *   PPML_POT_UNIFORM: Phi = gx x + gy y + gz z;  pot = {gx, gy, gz}      */
-typedef enum { PPML_POT_NONE = 0, PPML_POT_LOG = 1, PPML_POT_UNIFORM = 2 } ppml_potential;
+ *   PPML_POT_UNIFORM: Phi = gx x + gy y + gz z;  pot = {gx, gy, gz}
+ *   PPML_POT_HALO:    the dark-matter halo of Sec. 4, density
+ *                     rho0 / (1 + (r/r0)^2) out to the halo radius rh (r from
+ *                     (cx, cy, cz)); grad Phi = G M(r) / r^2 (radial, outward)
+ *                     with M(r) = 4 pi rho0 r0^3 (u - atan u), u = min(r, rh)/r0;
+ *                     pot = {G rho0, r0, rh, cx, cy, cz}, r0, rh > 0; 3-D
+ *                     grids, stepped alone (not in a batch)                */
+typedef enum { PPML_POT_NONE = 0, PPML_POT_LOG = 1, PPML_POT_UNIFORM = 2, PPML_POT_HALO = 3 } ppml_potential;
 
 /* Descriptor flags.  PPML_FLAG_FIRST_ORDER: piecewise-constant states in both
  * stages instead of parabolas -- the first-order scheme of Sec. 2.1 that the

@@ -20,7 +20,7 @@ _LIB = os.path.join(_HERE, "libppml_oracle.so")
 
 FIELDS = ("rho", "mx", "my", "mz", "Et", "e")
 BC = {"periodic": 0, "outflow": 1, "reflect": 2, "inflow": 3}
-POT = {None: 0, "none": 0, "log": 1, "uniform": 2}
+POT = {None: 0, "none": 0, "log": 1, "uniform": 2, "halo": 3}
 
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-std=c11"]
 

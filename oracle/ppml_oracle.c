@@ -50,7 +50,7 @@
 #define NF 6
 enum { F_RHO = 0, F_MX = 1, F_MY = 2, F_MZ = 3, F_ET = 4, F_E = 5 };
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2, BC_INFLOW = 3 };
-enum { POT_NONE = 0, POT_LOG = 1, POT_UNIFORM = 2 };
+enum { POT_NONE = 0, POT_LOG = 1, POT_UNIFORM = 2, POT_HALO = 3 };
 #define GH 3 /* ghost layers on each side of an active axis */
 
 typedef struct {
@@ -62,7 +62,8 @@ typedef struct {
     double gamma, cfl, vacuum_ratio, rho_mean0;
     int bc_lo[3], bc_hi[3];
     int potential;
-    double pot[8]; /* POT_LOG: v0, rc, q, cx, cy, cz ; POT_UNIFORM: gx, gy, gz */
+    double pot[8]; /* POT_LOG: v0, rc, q, cx, cy, cz ; POT_UNIFORM: gx, gy, gz ;
+                      POT_HALO: G rho0, r0, rh, cx, cy, cz */
     int first_order; /* 1: piecewise-constant states instead of parabolas */
     double inflow[6][NF]; /* conserved state of the ghost cells of inflow face
                              2*axis + side (0 low, 1 high)                 */
@@ -398,7 +399,10 @@ double og_dt(const og_grid *g)
 
 /* Gradient of the fixed external potential at a cell centre (eqs. (2)-(3)
  * force terms).  POT_LOG: Phi = v0^2/2 ln(rc^2 + X^2 + Y^2 + Z^2/q^2);
- * POT_UNIFORM: Phi = g . x. */
+ * POT_UNIFORM: Phi = g . x; POT_HALO: the dark-matter halo of Sec. 4,
+ * rho_DM = rho0 / (1 + (r/r0)^2) out to the halo radius rh, whose field is
+ * G M(r) / r^2 towards the centre with the enclosed mass
+ * M(r) = 4 pi rho0 r0^3 (u - atan u), u = min(r, rh) / r0. */
 static void potential_grad(const og_grid *g, long i, long j, long k, double *gr)
 {
     double x = g->lo[0] + ((double)i + 0.5) * g->h[0];
@@ -417,6 +421,20 @@ static void potential_grad(const og_grid *g, long i, long j, long k, double *gr)
         gr[0] = g->pot[0];
         gr[1] = g->pot[1];
         gr[2] = g->pot[2];
+    } else if (g->potential == POT_HALO) {
+        double X = x - g->pot[3], Y = y - g->pot[4], Z = z - g->pot[5];
+        double r = sqrt(X * X + Y * Y + Z * Z);
+        if (r > 0.0) {
+            double r0 = g->pot[1];
+            double u = (r < g->pot[2] ? r : g->pot[2]) / r0;
+            double m = 4.0 * M_PI * g->pot[0] * (r0 * r0 * r0) * (u - atan(u));
+            double a = m / (r * r * r);
+            gr[0] = a * X;
+            gr[1] = a * Y;
+            gr[2] = a * Z;
+        } else {
+            gr[0] = gr[1] = gr[2] = 0.0;
+        }
     } else {
         gr[0] = gr[1] = gr[2] = 0.0;
     }

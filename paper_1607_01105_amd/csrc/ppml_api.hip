@@ -115,9 +115,13 @@ int validate(const ppml_desc *d)
     if (!(d->gamma > 1.0) || !std::isfinite(d->gamma)) return fail(PPML_EINVAL, "gamma must be > 1");
     if (!(d->cfl > 0.0 && d->cfl < 1.0)) return fail(PPML_EINVAL, "cfl must lie in (0, 1)");
     if (!(d->vacuum_ratio >= 0.0)) return fail(PPML_EINVAL, "vacuum_ratio must be >= 0");
-    if (d->potential != PPML_POT_NONE && d->potential != PPML_POT_LOG && d->potential != PPML_POT_UNIFORM)
+    if (d->potential != PPML_POT_NONE && d->potential != PPML_POT_LOG && d->potential != PPML_POT_UNIFORM &&
+        d->potential != PPML_POT_HALO)
         return fail(PPML_EINVAL, "bad potential code");
     if (d->potential == PPML_POT_LOG && !(d->pot[2] > 0.0)) return fail(PPML_EINVAL, "log potential needs q > 0");
+    if (d->potential == PPML_POT_HALO && !(d->pot[1] > 0.0 && d->pot[2] > 0.0))
+        return fail(PPML_EINVAL, "halo potential needs r0 > 0 and rh > 0");
+    if (d->potential == PPML_POT_HALO && d->ndim != 3) return fail(PPML_EINVAL, "the halo potential needs ndim = 3");
     if (d->flags & ~(PPML_FLAG_FIRST_ORDER | PPML_FLAG_ISOTHERMAL)) return fail(PPML_EINVAL, "unknown flags 0x%x", d->flags);
     if ((d->flags & PPML_FLAG_ISOTHERMAL) && !(d->iso_cs > 0.0 && std::isfinite(d->iso_cs)))
         return fail(PPML_EINVAL, "the isothermal variant needs iso_cs > 0");
@@ -254,8 +258,10 @@ template <typename T, int NDIM> void launch_stages(ppml_grid *g, hipEvent_t *ev)
         const int nbl = gl.tiles[0] * gl.tiles[1] * gl.tiles[2];
         if (ev) (void)hipEventRecord(ev[1], g->stream);
         if constexpr (NDIM == 3) {
-            if (ge.self_grav)
-                k_euler<T, 3, TL::tx, TL::ty, true><<<nbe, TL::nt, 0, g->stream>>>(U, W, ge, g->ctrl);
+            if (ge.potential == POT_HALO)
+                k_euler<T, 3, TL::tx, TL::ty, 2><<<nbe, TL::nt, 0, g->stream>>>(U, W, ge, g->ctrl);
+            else if (ge.self_grav)
+                k_euler<T, 3, TL::tx, TL::ty, 1><<<nbe, TL::nt, 0, g->stream>>>(U, W, ge, g->ctrl);
             else
                 k_euler<T, 3, TL::tx, TL::ty><<<nbe, TL::nt, 0, g->stream>>>(U, W, ge, g->ctrl);
         } else {
@@ -472,15 +478,16 @@ int choose_chunks(long long tiles_xy, int nz, long long slots, double warm)
     return best;
 }
 
-template <typename T> void stage_slots(int device, int tile, bool sg, long long &slots_e, long long &slots_l)
+template <typename T> void stage_slots(int device, int tile, int xf, long long &slots_e, long long &slots_l)
 {
     int cus = 0, be = 0, bl = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 0;
     with_tile<3>(tile, [&](auto tl) {
         using TL = decltype(tl);
-        hipError_t e = sg ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&be, k_euler<T, 3, TL::tx, TL::ty, true>,
-                                                                         TL::nt, 0)
-                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&be, k_euler<T, 3, TL::tx, TL::ty>, TL::nt, 0);
+        hipError_t e =
+            xf == 2   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&be, k_euler<T, 3, TL::tx, TL::ty, 2>, TL::nt, 0)
+            : xf == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&be, k_euler<T, 3, TL::tx, TL::ty, 1>, TL::nt, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&be, k_euler<T, 3, TL::tx, TL::ty>, TL::nt, 0);
         if (e != hipSuccess) be = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bl, k_lagr<T, 3, TL::tx, TL::ty, LG<T>::g>, TL::nt, 0) !=
             hipSuccess)
@@ -666,8 +673,9 @@ int ppml_create(const ppml_desc *d, void *state_dev, void *scratch_dev, void *hi
         // stage kernel (start-up cost: 3 z-only planes in the Eulerian
         // kernel, 6 in the Lagrangian kernel)
         long long se, sl;
-        if (d->prec == PPML_FP64) stage_slots<double>(g->device, d->tile, gp.self_grav != 0, se, sl);
-        else stage_slots<float>(g->device, d->tile, gp.self_grav != 0, se, sl);
+        const int xf = gp.potential == POT_HALO ? 2 : (gp.self_grav ? 1 : 0);
+        if (d->prec == PPML_FP64) stage_slots<double>(g->device, d->tile, xf, se, sl);
+        else stage_slots<float>(g->device, d->tile, xf, se, sl);
         const long long txy = (long long)gp.tiles[0] * gp.tiles[1];
         set_chunks(g->gpE, choose_chunks(txy, gp.n[2], se, 1.5));
         set_chunks(g->gpL, choose_chunks(txy, gp.n[2], sl, 3.0));
@@ -1144,7 +1152,8 @@ int ppml_batch_admit(ppml_batch *b, ppml_grid *g, int32_t *slot)
     if (!g->has_state) return fail(PPML_ESTATE, "grid state was never set");
     if (g->device != b->device) return fail(PPML_EINVAL, "grid and batch live on different devices");
     if (b->prec >= 0 && g->d.prec != b->prec) return fail(PPML_EINVAL, "all grids of a batch share one precision");
-    if (g->gp.self_grav) return fail(PPML_EINVAL, "grids with self-gravity step alone, not in a batch");
+    if (g->gp.self_grav || g->gp.potential == POT_HALO)
+        return fail(PPML_EINVAL, "grids with self-gravity or the halo potential step alone, not in a batch");
     const size_t need = grid_bytes(g);
     if (b->budget > 0 && b->in_use + need > b->budget)
         return fail(PPML_EBUDGET, "admitting %zu bytes would exceed the budget (%zu of %zu in use)", need, b->in_use,

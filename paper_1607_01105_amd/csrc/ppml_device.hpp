@@ -18,7 +18,7 @@
 namespace ppml {
 
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2, BC_INFLOW = 3 };
-enum { POT_NONE = 0, POT_LOG = 1, POT_UNIFORM = 2 };
+enum { POT_NONE = 0, POT_LOG = 1, POT_UNIFORM = 2, POT_HALO = 3 };
 constexpr int GH = 3;  // ghost layers: a cell update reads q[i-3 .. i+3]
 
 // Per-grid constants passed by value to every kernel.
@@ -340,6 +340,9 @@ template <typename T> __device__ __forceinline__ T interface_velocity(T va, T sa
 }
 
 // Gradient of the fixed potential at a cell centre (eqs. (2)-(3) force terms).
+// XF = 2: the instantiation for halo grids, the only one that evaluates the
+// halo (its arctangent would cost the other grids registers).
+template <int XF>
 __device__ __forceinline__ void potential_grad(const GridParams &gp, int i, int j, int k, double g[3])
 {
     double x = gp.lo[0] + ((double)i + 0.5) * gp.h[0];
@@ -358,6 +361,22 @@ __device__ __forceinline__ void potential_grad(const GridParams &gp, int i, int 
         g[0] = gp.pot[0];
         g[1] = gp.pot[1];
         g[2] = gp.pot[2];
+    } else if (XF == 2 && gp.potential == POT_HALO) {
+        // dark-matter halo rho0 / (1 + (r/r0)^2) out to rh (Sec. 4): field
+        // G M(r) / r^2 with M(r) = 4 pi rho0 r0^3 (u - atan u), u = min(r, rh) / r0
+        const double X = x - gp.pot[3], Y = y - gp.pot[4], Z = z - gp.pot[5];
+        const double r = sqrt(X * X + Y * Y + Z * Z);
+        if (r > 0.0) {
+            const double r0 = gp.pot[1];
+            const double u = (r < gp.pot[2] ? r : gp.pot[2]) / r0;
+            const double m = 4.0 * M_PI * gp.pot[0] * (r0 * r0 * r0) * (u - atan(u));
+            const double a = m / (r * r * r);
+            g[0] = a * X;
+            g[1] = a * Y;
+            g[2] = a * Z;
+        } else {
+            g[0] = g[1] = g[2] = 0.0;
+        }
     } else {
         g[0] = g[1] = g[2] = 0.0;
     }

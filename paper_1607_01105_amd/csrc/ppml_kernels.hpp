@@ -187,9 +187,11 @@ __global__ __launch_bounds__(TOT_THREADS) void k_totals_final(const double *__re
 // ---------------------------------------------------------------------------
 // Eulerian stage
 // ---------------------------------------------------------------------------
-// SG: the grid has self-gravity (a separate instantiation, so the force's
-// loads of the potential cost the other grids no registers).
-template <typename T, int NDIM, int TX, int TY, bool SG = false>
+// XF: 1 for grids with self-gravity, 2 for grids in the halo potential (with
+// or without self-gravity); separate instantiations, so the loads of the
+// self-gravity potential and the halo's arctangent cost the other grids no
+// registers.
+template <typename T, int NDIM, int TX, int TY, int XF = 0>
 __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restrict__ Wst, const GridParams &gp,
                                            Ctrl *ctrl, const int bx, const int by, const int bz, const bool lead)
 {
@@ -511,10 +513,11 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
             mn[2] = mom[2] - tau * DPz;
             T Etn = Et - tau * sPV;
             T en = e - ((tau * gm1) * e) * sV;
-            if (SG || gp.potential != POT_NONE) {
+            if (XF != 0 || gp.potential != POT_NONE) {
                 double g[3];
-                potential_grad(gp, gx, gy, k, g);
-                if constexpr (SG && NDIM == 3) self_gravity_grad<T>(gp, gx, gy, k, g);
+                potential_grad<XF>(gp, gx, gy, k, g);
+                if constexpr (XF != 0 && NDIM == 3)
+                    if (gp.self_grav) self_gravity_grad<T>(gp, gx, gy, k, g);
                 const double work = (double)mom[0] * g[0] + (double)mom[1] * g[1] + (double)mom[2] * g[2];
                 const double tr = tau_d * (double)rho;
                 for (int ax = 0; ax < NDIM; ax++) mn[ax] = (T)((double)mn[ax] - tr * g[ax]);
@@ -530,13 +533,13 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
     }
 }
 
-template <typename T, int NDIM, int TX, int TY, bool SG = false>
+template <typename T, int NDIM, int TX, int TY, int XF = 0>
 __global__ __launch_bounds__(TX *TY) void k_euler(const T *__restrict__ U, T *__restrict__ Wst, GridParams gp,
                                                    Ctrl *ctrl)
 {
     int bx, by, bz;
     block_tile(gp, bx, by, bz);
-    euler_body<T, NDIM, TX, TY, SG>(U, Wst, gp, ctrl, bx, by, bz, blockIdx.x == 0 && threadIdx.x == 0);
+    euler_body<T, NDIM, TX, TY, XF>(U, Wst, gp, ctrl, bx, by, bz, blockIdx.x == 0 && threadIdx.x == 0);
 }
 
 // ---------------------------------------------------------------------------

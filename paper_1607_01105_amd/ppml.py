@@ -20,12 +20,13 @@ PPML_OK, PPML_EINVAL, PPML_ENOMEM, PPML_EHIP, PPML_ENONFINITE, PPML_EBUDGET, PPM
 PPML_FP32, PPML_FP64 = 0, 1
 PPML_PERIODIC, PPML_OUTFLOW, PPML_REFLECT, PPML_INFLOW = 0, 1, 2, 3
 PPML_RHO, PPML_MX, PPML_MY, PPML_MZ, PPML_ETOT, PPML_EINT = 0, 1, 2, 3, 4, 5
-PPML_POT_NONE, PPML_POT_LOG, PPML_POT_UNIFORM = 0, 1, 2
+PPML_POT_NONE, PPML_POT_LOG, PPML_POT_UNIFORM, PPML_POT_HALO = 0, 1, 2, 3
 PPML_FLAG_FIRST_ORDER, PPML_FLAG_ISOTHERMAL = 1, 2
 
 BC = {"periodic": PPML_PERIODIC, "outflow": PPML_OUTFLOW, "reflect": PPML_REFLECT, "inflow": PPML_INFLOW}
 PREC = {"fp32": PPML_FP32, "f32": PPML_FP32, "fp64": PPML_FP64, "f64": PPML_FP64}
-POT = {None: PPML_POT_NONE, "none": PPML_POT_NONE, "log": PPML_POT_LOG, "uniform": PPML_POT_UNIFORM}
+POT = {None: PPML_POT_NONE, "none": PPML_POT_NONE, "log": PPML_POT_LOG, "uniform": PPML_POT_UNIFORM,
+       "halo": PPML_POT_HALO}
 
 
 class ppml_desc(C.Structure):

@@ -324,35 +324,45 @@ def gravity_sphere(n: int | tuple = 32, L: float = 2.0, G: float = 1.0, rho_floo
     return prob
 
 
-def galaxy_disk(n: int = 256, seed: int = 0, v0: float = 1.0, rc: float = 0.02, rd: float = 0.1,
-                cs: float = 0.05, G: float = 1.0, cfl: float = 0.2, rho_floor: float = 1e-3,
-                noise: float = 1e-4, gamma: float = 5.0 / 3.0) -> Problem:
+def galaxy_disk(n: int = 256, seed: int = 0, v0: float = 1.0, r0: float = 0.05, rh_over_r0: float = 78.55 / 1.6,
+                rd: float = 0.1, cs: float = 0.05, G: float = 1.0, cfl: float = 0.2, rho_floor: float = 1e-3,
+                noise: float = 1e-4, gamma: float = 5.0 / 3.0, halo: str = "paper") -> Problem:
     """The configuration of the paper's galactic-disk runs (Sec. 4) with
-    synthetic data: a self-gravitating isothermal gas disk in a fixed halo
-    potential, on an n^3 mesh of the box [-1/2, 1/2]^3.  The halo is the
-    logarithmic potential of the disk workload (flat rotation curve v0), the
-    disk has surface density exp(-R/rd), a Gaussian vertical profile of
-    scale height max(cs/v0 sqrt(R^2+rc^2), 2h), the halo's rotation curve
-    (the disk's own gravity is not balanced, so the disk contracts and, at
-    Toomre Q below 1, fragments), p = cs^2 rho (isothermal), a floor density
-    and a seeded lognormal density perturbation of rms 1e-4 as in the paper;
-    G = 1, outflow boundaries, CFL 0.2 (the paper's)."""
+    synthetic data: a self-gravitating isothermal gas disk in a fixed dark
+    matter halo, on an n^3 mesh of the box [-1/2, 1/2]^3.  halo = "paper":
+    the paper's halo density rho0 / (1 + (r/r0)^2) out to rh (its ratio
+    rh / r0 = 78.55 / 1.6), rho0 set so that the circular speed tends to v0;
+    halo = "log": the logarithmic potential of the disk workload with core r0.
+    The disk has surface density exp(-R/rd), a Gaussian vertical profile of
+    scale height max(cs/v0 sqrt(R^2+r0^2), 2h), the halo's rotation curve (the
+    disk's own gravity is not balanced, so the disk contracts and, at Toomre Q
+    below 1, fragments), p = cs^2 rho (isothermal), a floor density and a
+    seeded lognormal density perturbation of rms 1e-4 as in the paper; G = 1,
+    outflow boundaries, CFL 0.2 (the paper's)."""
     h = 1.0 / n
     lo, hi = (-0.5,) * 3, (0.5,) * 3
     n3 = (n, n, n)
     X, Y, Z = _mesh(n3, lo, hi)
     R = np.sqrt(X * X + Y * Y)
-    H = np.maximum((cs / v0) * np.sqrt(R * R + rc * rc), 2.0 * h)
+    H = np.maximum((cs / v0) * np.sqrt(R * R + r0 * r0), 2.0 * h)
     rho = np.exp(-R / rd) / (math.sqrt(2.0 * math.pi) * H) * np.exp(-Z * Z / (2.0 * H * H))
     rho = np.maximum(rho, rho_floor)
     rho = rho * np.exp(noise * np.random.default_rng(seed).standard_normal(rho.shape))
-    vphi = v0 * R / np.sqrt(R * R + rc * rc)
+    if halo == "paper":
+        # circular speed of the halo: v^2 = G M(R) / R = v0^2 (1 - atan(u) / u), u = R / r0
+        u = R / r0
+        with np.errstate(invalid="ignore", divide="ignore"):
+            vphi = v0 * np.sqrt(np.where(u > 0, 1.0 - np.arctan(u) / np.where(u > 0, u, 1.0), 0.0))
+        pot = ("halo", v0 * v0 / (4.0 * math.pi * r0 * r0), r0, r0 * rh_over_r0, 0.0, 0.0, 0.0)
+    else:
+        vphi = v0 * R / np.sqrt(R * R + r0 * r0)
+        pot = ("log", v0, r0, 1.0, 0.0, 0.0, 0.0)
     with np.errstate(invalid="ignore", divide="ignore"):
         cx = np.where(R > 0, -Y / R, 0.0)
         cy = np.where(R > 0, X / R, 0.0)
-    prob = Problem(f"galaxy_disk_{n}_s{seed}", 3, n3, lo, hi, gamma, cfl, [("outflow", "outflow")] * 3,
+    prob = Problem(f"galaxy_disk_{n}_s{seed}_{halo}", 3, n3, lo, hi, gamma, cfl, [("outflow", "outflow")] * 3,
                    np.ascontiguousarray(rho), np.ascontiguousarray(vphi * cx), np.ascontiguousarray(vphi * cy),
-                   np.zeros(X.shape), np.ascontiguousarray(rho * cs * cs), ("log", v0, rc, 1.0, 0.0, 0.0, 0.0))
+                   np.zeros(X.shape), np.ascontiguousarray(rho * cs * cs), pot)
     prob.isothermal = cs
     prob.self_gravity = G
     return prob

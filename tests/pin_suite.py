@@ -315,6 +315,35 @@ def pin_log_potential_force(lib=None):
         assert np.allclose(o.get(1 + a), -tau * 2.0 * grad[a], rtol=0, atol=2e-3 * tau), a
 
 
+def pin_halo_potential_force(lib=None):
+    """Gas at rest at uniform pressure in the dark-matter halo of Sec. 4
+    (density rho0 / (1 + (r/r0)^2) out to rh, centre off the grid): after one
+    short step rho v = -tau rho G M(r) / r^2 (radial), with the enclosed mass
+    M(r) integrated numerically from the halo density (not from the closed
+    form), inside and beyond the halo radius."""
+    from scipy.integrate import quad
+
+    n = 10
+    Grho0, r0, rh, c = 0.8, 0.15, 0.35, (0.03, -0.02, 0.05)
+    o = oracle.Oracle(3, (n, n, n), (-0.5,) * 3, (0.5,) * 3, 1.4, 0.3, bc="periodic",
+                      potential=("halo", Grho0, r0, rh) + c, lib=_lib(lib))
+    shp = (n, n, n)
+    z = np.zeros(shp)
+    o.set_primitive(np.full(shp, 2.0), z, z, z, np.full(shp, 1.0))
+    tau = 1e-7
+    o.step(tau)
+    xs = -0.5 + (np.arange(n) + 0.5) / n
+    Z, Y, X = np.meshgrid(xs - c[2], xs - c[1], xs - c[0], indexing="ij")
+    R = np.sqrt(X * X + Y * Y + Z * Z)
+    mass = np.vectorize(lambda r: quad(lambda s: 4 * math.pi * s * s / (1 + (s / r0) ** 2), 0.0, min(r, rh),
+                                       epsabs=0.0, epsrel=1e-13)[0])
+    a = Grho0 * mass(R) / R ** 3
+    assert np.any(R > rh) and np.any(R < r0)
+    for ax, Xa in enumerate((X, Y, Z)):
+        ref = -tau * 2.0 * a * Xa
+        assert np.allclose(o.get(1 + ax), ref, rtol=1e-9, atol=1e-9 * float(np.max(np.abs(ref)))), ax
+
+
 # --------------------------------------------------------------------------
 # Closed-form solutions
 # --------------------------------------------------------------------------

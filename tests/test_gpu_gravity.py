@@ -260,3 +260,49 @@ def test_galaxy_disk_configuration_vs_oracle():
     l1 = float(np.sum(np.abs(g32.get("rho") - r64)) / np.sum(r64))
     print(f"galaxy 40^3 fp32: L1(rho) {l1:.3e}", flush=True)
     assert l1 <= 1e-4
+
+
+def _halo_problem():
+    prob = W.random_smooth(3, (24, 20, 18), seed=81, bc="outflow")
+    prob.lo = (-0.5, -0.5, -0.5)
+    prob.hi = (0.5, 0.5, 0.5)
+    prob.potential = ("halo", 0.8, 0.15, 0.35, 0.03, -0.02, 0.05)
+    prob.name += "_halo"
+    return prob
+
+
+def test_halo_potential_vs_oracle():
+    """The dark-matter halo of Sec. 4 as the fixed potential: FP64 within
+    1e-11 of the oracle in both builds (the arctangent of the GPU's math
+    library and the host's may differ in the last bit), FP32 within 1e-4 (L1,
+    density); every tile shape gives the same bits; batches refuse the grid."""
+    from paper_1607_01105_amd import ppml
+    from paper_1607_01105_amd.ppml import Batch, ppml_tile_count
+
+    prob = _halo_problem()
+    o = make_oracle(prob)
+    taus = o.run(10)
+    for exact in (True, False):
+        g = _grid(prob, exact=exact)
+        for tau in taus:
+            g.step(1, dt_fixed=float(tau))
+        for f in range(6):
+            err = _rel(g.get(f), o.get(f))
+            assert err <= 1e-11, (exact, f, err)
+    g32 = _grid(prob, prec="fp32")
+    for tau in taus:
+        g32.step(1, dt_fixed=float(tau))
+    r64 = o.get("rho")
+    assert float(np.sum(np.abs(g32.get("rho") - r64)) / np.sum(r64)) <= 1e-4
+    ref = None
+    for v in range(ppml_tile_count(3)):
+        g = _grid(prob, exact=True, tile=v)
+        g.step(5)
+        out = [g.get(f) for f in range(6)]
+        if ref is None:
+            ref = out
+        for a, b in zip(out, ref):
+            assert np.array_equal(a, b), v
+    b = Batch(capacity=2)
+    with pytest.raises(ppml.PPMLError):
+        b.admit(_grid(prob, prec="fp32"))

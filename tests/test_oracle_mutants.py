@@ -87,6 +87,9 @@ MUTANTS = [
     ("gravity_gradient_h", "double h2 = 2.0 * g->h[0];", "double h2 = g->h[0];"),
     ("gravity_gradient_axis", "gr[1] = (g->phi[pidx(g, i, j + 1, k)] - g->phi[pidx(g, i, j - 1, k)]) / h2;",
      "gr[1] = (g->phi[pidx(g, i + 1, j, k)] - g->phi[pidx(g, i - 1, j, k)]) / h2;"),
+    ("halo_mass_sign", "(u - atan(u));", "(u + atan(u));"),
+    ("halo_r0_power", "g->pot[0] * (r0 * r0 * r0) *", "g->pot[0] * (r0 * r0) *"),
+    ("halo_truncation", "double u = (r < g->pot[2] ? r : g->pot[2]) / r0;", "double u = r / r0;"),
     ("iso_pressure", "qp[m] = g->iso ? (g->cs * g->cs) * r", "qp[m] = g->iso ? g->cs * r"),
     ("iso_riemann_gamma", "const double gam = g->iso ? 1.0 : g->gamma;", "const double gam = g->gamma;"),
     ("iso_cfl_speed", "double c = sqrt((g->iso ? 1.0 : g->gamma) * p / r);", "double c = sqrt(g->gamma * p / r);"),
