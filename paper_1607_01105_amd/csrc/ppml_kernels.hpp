@@ -211,13 +211,26 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
     constexpr int NXI = (TX + 1) * TY;
     constexpr int NYI = NDIM >= 2 ? TX * (TY + 1) : 1;
 
-    __shared__ T s_vx[PS];
-    __shared__ T s_vy[NDIM >= 2 ? PS : 1];
-    __shared__ T s_p[PS], s_s[PS], s_r32[PS], s_ps[PS];
+    // The velocity and pressure tiles (read by the parabola jobs) and the
+    // interface states (written by the Riemann jobs, read by the update) are
+    // never live at once.  FP64 overlays them, which brings a 16x16 or 32x8
+    // tile under a third of the CU's LDS, at the price of one barrier per
+    // plane before the tiles are rewritten; FP32 tiles are small enough
+    // already and keep them apart.
+    constexpr bool OVERLAY = sizeof(T) == 8;
+    constexpr int NVY = NDIM >= 2 ? PS : 1;
+    constexpr size_t B_TILE = ((size_t)(2 * PS + NVY) * sizeof(T) + 15) & ~(size_t)15;
+    constexpr size_t B_IFACE = (size_t)(NXI + NYI) * sizeof(VP<T>);
+    constexpr size_t B_UNION = OVERLAY ? (B_TILE > B_IFACE ? B_TILE : B_IFACE) : B_TILE + B_IFACE;
+    __shared__ __align__(16) unsigned char s_union[B_UNION];
+    T *const s_vx = reinterpret_cast<T *>(s_union);
+    T *const s_vy = s_vx + PS;
+    T *const s_p = s_vy + NVY;
+    VP<T> *const xi = reinterpret_cast<VP<T> *>(s_union + (OVERLAY ? 0 : B_TILE));
+    VP<T> *const yi = xi + NXI;
+    __shared__ T s_s[PS], s_r32[PS], s_ps[PS];
     __shared__ Parab<T> xv[NXP], xp[NXP];
     __shared__ Parab<T> yv[NYP], yp[NYP];
-    __shared__ VP<T> xi[NXI];
-    __shared__ VP<T> yi[NYI];
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
@@ -372,6 +385,9 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
             if constexpr (NDIM >= 2) xr[r][2] = Uf[2][c];
             xr[r][NDIM + 1] = Uf[2 + NDIM][c];
         }
+        // overlaid tiles: the previous plane's update has read its interface
+        // states before they are overwritten (the loads above are in flight)
+        if constexpr (OVERLAY) __syncthreads();
 #pragma unroll
         for (int r = 0; r < RC; r++) {
             if (ccode[r] < 0) continue;
