@@ -131,8 +131,8 @@ typedef struct {
  * stencil's eigenvalues and the inverse transforms.  The force terms of
  * eqs. (2)-(3) then use the central difference of the potential across each
  * cell, added to any fixed potential's gradient.  The scratch area grows by
- * the potential, two work arrays of the grid's size and the sine tables
- * (see ppml_scratch_bytes).  Grids with self-gravity step alone, not in a
+ * the potential, two work arrays of the grid's size, the shell terms of the
+ * outer layer of cells and the sine tables (see ppml_scratch_bytes).  Grids with self-gravity step alone, not in a
  * batch. */
 
 /* Work-group tile shapes of the stage kernels for grids of ndim dimensions:

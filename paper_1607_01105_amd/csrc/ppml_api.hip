@@ -158,8 +158,8 @@ int totals_blocks(long long n) { return (int)std::min<long long>(1024, (n + 4095
 struct ScratchLayout {
     size_t half, ctrl, partial, totals;
     // self-gravity: padded potential, two work arrays, sine matrices,
-    // eigenvalue factors, moment partials
-    size_t phi, wx, wy, sx, sy, sz, fx, fy, fz, gpart;
+    // eigenvalue factors, moment partials, shell terms of the outer layer
+    size_t phi, wx, wy, sx, sy, sz, fx, fy, fz, gpart, gedge;
     size_t total;
 };
 
@@ -177,7 +177,7 @@ ScratchLayout layout(const ppml_desc *d)
     sz += align_up((size_t)totals_blocks(ncells(d)) * 6 * sizeof(double));
     L.totals = sz;
     sz += align_up(8 * sizeof(double));
-    L.phi = L.wx = L.wy = L.sx = L.sy = L.sz = L.fx = L.fy = L.fz = L.gpart = 0;
+    L.phi = L.wx = L.wy = L.sx = L.sy = L.sz = L.fx = L.fy = L.fz = L.gpart = L.gedge = 0;
     if (d->self_gravity) {
         const size_t e = elem(d);
         const size_t n0 = (size_t)d->n[0], n1 = (size_t)d->n[1], n2 = (size_t)d->n[2];
@@ -201,6 +201,8 @@ ScratchLayout layout(const ppml_desc *d)
         sz += align_up(n2 * sizeof(double));
         L.gpart = sz;
         sz += align_up((size_t)grav_blocks(ncells(d)) * GRAV_MOM * sizeof(double));
+        L.gedge = sz;
+        sz += align_up((size_t)grav_edge_cells(d->n[0], d->n[1], d->n[2]) * e);
     }
     L.total = sz;
     return L;
@@ -226,7 +228,7 @@ struct ppml_grid {
     long long timed;             // steps recorded since the last read
     // self-gravity (Sec. 2.5)
     rocblas_handle blas;
-    void *phi, *wx, *wy, *sx, *sy, *sz;
+    void *phi, *wx, *wy, *sx, *sy, *sz, *gedge;
     double *fx, *fy, *fz, *gpart;
     double grav_coef;      // 4 pi G h^2
     double grav_norm;      // prod_a 2 / (n_a + 1)
@@ -346,19 +348,20 @@ template <typename T> int launch_gravity(ppml_grid *g)
     k_grav_moments_final<<<1, GRAV_THREADS, 0, g->stream>>>(g->gpart, nb, g->ctrl);
     const long long nshell = (long long)(n0 + 2) * (n1 + 2) * (n2 + 2) - N;
     k_grav_shell<T><<<(unsigned)((nshell + 255) / 256), 256, 0, g->stream>>>(gp, g->ctrl, g->d.grav_G, phi);
-    const unsigned nbc = (unsigned)((N + 255) / 256);
-    k_grav_rhs<T><<<nbc, 256, 0, g->stream>>>(rho, gp, g->grav_coef, X);
+    // shell terms of the outer layer, then the right-hand side's sums and
+    // differences into Y
+    T *E = (T *)g->gedge;
     const long long nedge = grav_edge_cells(n0, n1, n2);
-    k_grav_rhs_edge<T><<<(unsigned)((nedge + 255) / 256), 256, 0, g->stream>>>(rho, phi, gp, g->grav_coef, X);
+    k_grav_edge_terms<T><<<(unsigned)((nedge + 255) / 256), 256, 0, g->stream>>>(phi, gp, E);
     const long long nrep = (long long)grav_no(n0) * grav_no(n1) * grav_no(n2);
     const unsigned nbr = (unsigned)((nrep + 255) / 256);
-    k_grav_butterfly<T><<<nbr, 256, 0, g->stream>>>(X, Y, gp);
+    k_grav_butterfly<T><<<nbr, 256, 0, g->stream>>>(rho, E, g->grav_coef, Y, gp);
     HIPCHK(hipGetLastError());
     int rc;
     if ((rc = sine_transform<T>(g, 0, false, Y, X))) return rc;
     if ((rc = sine_transform<T>(g, 1, false, X, Y))) return rc;
     if ((rc = sine_transform<T>(g, 2, false, Y, X))) return rc;
-    const dim3 ged((unsigned)((n0 + 255) / 256), (unsigned)std::min(rows, 32768));
+    const dim3 ged((unsigned)((n0 + 255) / 256), (unsigned)std::min((rows + 3) / 4, 4096));
     k_grav_eigdiv<T><<<ged, 256, 0, g->stream>>>(X, g->fx, g->fy, g->fz, gp, g->grav_norm);
     HIPCHK(hipGetLastError());
     if ((rc = sine_transform<T>(g, 2, true, X, Y))) return rc;
@@ -623,7 +626,7 @@ int ppml_create(const ppml_desc *d, void *state_dev, void *scratch_dev, void *hi
         }
     }
     g->blas = nullptr;
-    g->phi = g->wx = g->wy = g->sx = g->sy = g->sz = nullptr;
+    g->phi = g->wx = g->wy = g->sx = g->sy = g->sz = g->gedge = nullptr;
     g->fx = g->fy = g->fz = g->gpart = nullptr;
     if (d->self_gravity) {
         g->phi = s + L.phi;
@@ -636,6 +639,7 @@ int ppml_create(const ppml_desc *d, void *state_dev, void *scratch_dev, void *hi
         g->fy = (double *)(s + L.fy);
         g->fz = (double *)(s + L.fz);
         g->gpart = (double *)(s + L.gpart);
+        g->gedge = s + L.gedge;
         gp.self_grav = 1;
         gp.phi = g->phi;
         const double h = gp.h[0];

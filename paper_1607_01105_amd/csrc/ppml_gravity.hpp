@@ -9,14 +9,17 @@
 //   2. k_grav_shell: the one-cell shell around the box takes the two-term
 //      multipole expansion (monopole and quadrupole, MacCullagh's form with
 //      its factor 1/2) -- stage 1;
-//   3. k_grav_rhs: 4 pi G h^2 rho minus the stencil terms that reach the
-//      shell (the boundary values move to the right-hand side);
+//   3. right-hand side 4 pi G h^2 rho minus the stencil terms that reach
+//      the shell (the boundary values move to the right-hand side):
+//      k_grav_edge_terms forms the shell terms of the outer layer of cells,
+//      k_grav_butterfly adds them to 4 pi G h^2 rho as it reads the density;
 //   4. sine transforms along x, y, z (stage 2) -- products with the sine
 //      matrices sin(pi j k / (N+1)), which diagonalise the Dirichlet problem
 //      (the Fourier basis of the odd extension).  The matrix is split by the
 //      symmetry sin(pi j (N+1-k) / (N+1)) = -(-1)^j sin(pi j k / (N+1)): the
 //      odd modes need only the sums x_k + x_{N+1-k}, the even modes only the
-//      differences, so k_grav_butterfly forms sums and differences along all
+//      differences, so k_grav_butterfly forms sums and differences of the
+//      right-hand side along all
 //      three axes at once and each axis transform is two half-size GEMMs on
 //      the matrix cores (half the work of the full product), run by the host
 //      code; the modes come out odd first, then even, along each axis;
@@ -88,74 +91,110 @@ __global__ void k_grav_tables(T *__restrict__ Sx, T *__restrict__ Sy, T *__restr
     else if (t < c0 + c1 + c2) grav_table_entry<T>(Sz, fz, n2, t - c0 - c1);
 }
 
-__device__ __forceinline__ double block_sum(double v, double *sh)
-{
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int w = GRAV_THREADS / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + w];
-        __syncthreads();
-    }
-    const double r = sh[0];
-    __syncthreads();
-    return r;
-}
-
 // Stage 1, moments: block b sums the x rows [b chunk, (b+1) chunk) of the
 // grid (row r = j + n1 k; thread t takes columns i = t, t + GRAV_THREADS, ...
-// and runs down the block's rows, U loads in flight, then a fixed tree), so
-// the order of every sum is fixed by the grid size alone.
+// and runs down the block's rows, U loads in flight, then a fixed-order
+// reduction), so the order of every sum is fixed by the grid size alone.
+// x is fixed along a
+// thread's column, so the thread sums rho, y rho, z rho, y^2 rho, z^2 rho and
+// y z rho and forms the seven moments from them and x once per column; the
+// cell volume is applied once per block.
 template <typename T>
 __global__ __launch_bounds__(GRAV_THREADS) void k_grav_moments_partial(const T *__restrict__ rho, GridParams gp,
                                                                        int chunk, double *__restrict__ part)
 {
-    __shared__ double sh[GRAV_THREADS];
     const int n0 = gp.n[0], n1 = gp.n[1];
     const int rows = n1 * gp.n[2];
     const int r0 = blockIdx.x * chunk;
     const int r1 = r0 + chunk < rows ? r0 + chunk : rows;
     const double vol = gp.h[0] * gp.h[1] * gp.h[2];
     double s[GRAV_MOM] = {0, 0, 0, 0, 0, 0, 0};
-    constexpr int U = 8;  // loads in flight per thread
+    constexpr int U = 16;  // loads in flight per thread
     for (int i = threadIdx.x; i < n0; i += GRAV_THREADS) {
         const double x = gp.lo[0] + ((double)i + 0.5) * gp.h[0];
+        double a0 = 0, ay = 0, az = 0, ayy = 0, azz = 0, ayz = 0;
+        // (j, k) of the first row of each group of U, advanced without a
+        // division (uniform over the block)
+        int k0 = r0 / n1, j0 = r0 - k0 * n1;
         for (int rb = r0; rb < r1; rb += U) {
             T v[U];
 #pragma unroll
             for (int u = 0; u < U; u++) v[u] = rb + u < r1 ? rho[(long long)(rb + u) * n0 + i] : T(0);
+            int j = j0, k = k0;
 #pragma unroll
             for (int u = 0; u < U; u++) {
-                const int row = rb + u;
-                if (row >= r1) break;
-                const int k = row / n1, j = row - k * n1;
+                if (rb + u >= r1) break;
                 const double y = gp.lo[1] + ((double)j + 0.5) * gp.h[1];
                 const double z = gp.lo[2] + ((double)k + 0.5) * gp.h[2];
-                const double m = (double)v[u] * vol;
-                s[0] = s[0] + m;
-                s[1] = s[1] + (y * y + z * z) * m;
-                s[2] = s[2] + (x * x + z * z) * m;
-                s[3] = s[3] + (x * x + y * y) * m;
-                s[4] = s[4] + x * y * m;
-                s[5] = s[5] + x * z * m;
-                s[6] = s[6] + y * z * m;
+                const double m = (double)v[u];
+                const double ym = y * m, zm = z * m;
+                a0 = a0 + m;
+                ay = ay + ym;
+                az = az + zm;
+                ayy = ayy + y * ym;
+                azz = azz + z * zm;
+                ayz = ayz + y * zm;
+                if (++j == n1) {
+                    j = 0;
+                    ++k;
+                }
             }
+            j0 = j;
+            k0 = k;
         }
+        const double xx = x * x;
+        s[0] = s[0] + a0;
+        s[1] = s[1] + (ayy + azz);
+        s[2] = s[2] + (xx * a0 + azz);
+        s[3] = s[3] + (xx * a0 + ayy);
+        s[4] = s[4] + x * ay;
+        s[5] = s[5] + x * az;
+        s[6] = s[6] + ayz;
     }
+    // fixed-order reduction: butterfly within each wave, then the waves'
+    // sums in order
+    __shared__ double shw[GRAV_THREADS / 64][GRAV_MOM];
+#pragma unroll
     for (int q = 0; q < GRAV_MOM; q++) {
-        const double r = block_sum(s[q], sh);
-        if (threadIdx.x == 0) part[(long long)blockIdx.x * GRAV_MOM + q] = r;
+        double v = s[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v = v + __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) shw[threadIdx.x >> 6][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < GRAV_MOM) {
+        double r = 0.0;
+#pragma unroll
+        for (int w = 0; w < GRAV_THREADS / 64; w++) r = r + shw[w][threadIdx.x];
+        part[(long long)blockIdx.x * GRAV_MOM + threadIdx.x] = r * vol;
     }
 }
 
 __global__ __launch_bounds__(GRAV_THREADS) void k_grav_moments_final(const double *__restrict__ part, int nb,
                                                                      Ctrl *ctrl)
 {
-    __shared__ double sh[GRAV_THREADS];
+    // thread t sums the blocks t, t + GRAV_THREADS, ... in order, then the
+    // same fixed-order reduction as the partial sums
+    double s[GRAV_MOM];
+#pragma unroll
+    for (int q = 0; q < GRAV_MOM; q++) s[q] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += GRAV_THREADS)
+#pragma unroll
+        for (int q = 0; q < GRAV_MOM; q++) s[q] = s[q] + part[(long long)b * GRAV_MOM + q];
+    __shared__ double shw[GRAV_THREADS / 64][GRAV_MOM];
+#pragma unroll
     for (int q = 0; q < GRAV_MOM; q++) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nb; b += GRAV_THREADS) s = s + part[(long long)b * GRAV_MOM + q];
-        const double r = block_sum(s, sh);
-        if (threadIdx.x == 0) ctrl->mom[q] = r;
+        double v = s[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v = v + __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) shw[threadIdx.x >> 6][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < GRAV_MOM) {
+        double r = 0.0;
+#pragma unroll
+        for (int w = 0; w < GRAV_THREADS / 64; w++) r = r + shw[w][threadIdx.x];
+        ctrl->mom[threadIdx.x] = r;
     }
 }
 
@@ -208,24 +247,14 @@ __global__ void k_grav_shell(GridParams gp, const Ctrl *__restrict__ ctrl, doubl
     phi[pad_index(gp, i, j, k)] = (T)v;
 }
 
-// Right-hand side of the interior cells, first pass: coef rho (coef =
-// 4 pi G h^2) everywhere (a plain stream).
+// Shell terms of the right-hand side, over the outer layer of interior
+// cells only (the two z planes, the two y rows of the other planes, the two
+// x ends of the other rows; a cell listed twice on a grid of extent 1 or 2
+// gets the same value twice): minus the stencil's weight times every shell
+// value the cell's stencil touches, in the stencil's (dz, dy, dx) order,
+// into E[s] for the cell's place s in that list.
 template <typename T>
-__global__ void k_grav_rhs(const T *__restrict__ rho, GridParams gp, double coef, T *__restrict__ X)
-{
-    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= gp.ncell) return;
-    X[c] = (T)(coef * (double)rho[c]);
-}
-
-// Second pass over the outer layer of interior cells only (the two z
-// planes, the two y rows of the other planes, the two x ends of the other
-// rows; a cell listed twice on a grid of extent 1 or 2 gets the same value
-// twice): coef rho minus the stencil's weight times every shell value the
-// cell's stencil touches, in the stencil's (dz, dy, dx) order.
-template <typename T>
-__global__ void k_grav_rhs_edge(const T *__restrict__ rho, const T *__restrict__ phi, GridParams gp, double coef,
-                                T *__restrict__ X)
+__global__ void k_grav_edge_terms(const T *__restrict__ phi, GridParams gp, T *__restrict__ E)
 {
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int n0 = gp.n[0], n1 = gp.n[1], n2 = gp.n[2];
@@ -253,23 +282,33 @@ __global__ void k_grav_rhs_edge(const T *__restrict__ rho, const T *__restrict__
     } else {
         return;
     }
-    const long long c = ((long long)k * n1 + j) * n0 + i;
-    double b = coef * (double)rho[c];
-    {
-        for (int dz = -1; dz <= 1; dz++)
-            for (int dy = -1; dy <= 1; dy++)
-                for (int dx = -1; dx <= 1; dx++) {
-                    const int ii = i + dx, jj = j + dy, kk = k + dz;
-                    if (ii >= 0 && ii < n0 && jj >= 0 && jj < n1 && kk >= 0 && kk < n2) continue;
-                    const int nd = (dx != 0) + (dy != 0) + (dz != 0);
-                    const double w = nd == 1 ? 4.0 / 9.0 : (nd == 2 ? 1.0 / 9.0 : 1.0 / 36.0);
-                    b = b - w * (double)phi[pad_index(gp, ii, jj, kk)];
-                }
-    }
-    X[c] = (T)b;
+    double b = 0.0;
+    for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++) {
+                const int ii = i + dx, jj = j + dy, kk = k + dz;
+                if (ii >= 0 && ii < n0 && jj >= 0 && jj < n1 && kk >= 0 && kk < n2) continue;
+                const int nd = (dx != 0) + (dy != 0) + (dz != 0);
+                const double w = nd == 1 ? 4.0 / 9.0 : (nd == 2 ? 1.0 / 9.0 : 1.0 / 36.0);
+                b = b - w * (double)phi[pad_index(gp, ii, jj, kk)];
+            }
+    E[s] = (T)b;
 }
 
-// Cells of the outer layer listed by k_grav_rhs_edge.
+// Place of cell (i, j, k) in the outer-layer list of k_grav_edge_terms (its
+// first place where listed twice), -1 for a cell inside the layer.
+__device__ __forceinline__ long long grav_edge_index(int i, int j, int k, int n0, int n1, int n2)
+{
+    const long long P = (long long)n0 * n1;
+    const long long m2 = n2 > 2 ? n2 - 2 : 0, m1 = n1 > 2 ? n1 - 2 : 0;
+    if (k == 0) return (long long)j * n0 + i;
+    if (k == n2 - 1) return P + (long long)j * n0 + i;
+    if (j == 0 || j == n1 - 1) return 2 * P + (2ll * (k - 1) + (j == 0 ? 0 : 1)) * n0 + i;
+    if (i == 0 || i == n0 - 1) return 2 * P + 2 * m2 * n0 + (long long)(k - 1) * 2 * m1 + 2ll * (j - 1) + (i == 0 ? 0 : 1);
+    return -1;
+}
+
+// Cells of the outer layer listed by k_grav_edge_terms.
 __host__ __device__ inline long long grav_edge_cells(int n0, int n1, int n2)
 {
     const long long m2 = n2 > 2 ? n2 - 2 : 0, m1 = n1 > 2 ? n1 - 2 : 0;
@@ -316,12 +355,14 @@ __device__ __forceinline__ void grav_pairs(double a[2][2][2])
         }
 }
 
-// Sums and differences of mirror cells along x, y and z: X in cell order ->
-// Y in (sum | difference) slots per axis.  Along an axis the pair (p, n-1-p),
-// p < ne, gives slot p the sum and slot no + p the difference; a middle cell
-// (n odd) is its own sum.
+// Right-hand side of the cells (coef rho, coef = 4 pi G h^2, plus the shell
+// terms E of the outer layer) and its sums and differences of mirror cells
+// along x, y and z: Y in (sum | difference) slots per axis.  Along an axis
+// the pair (p, n-1-p), p < ne, gives slot p the sum and slot no + p the
+// difference; a middle cell (n odd) is its own sum.
 template <typename T>
-__global__ void k_grav_butterfly(const T *__restrict__ X, T *__restrict__ Y, GridParams gp)
+__global__ void k_grav_butterfly(const T *__restrict__ rho, const T *__restrict__ E, double coef,
+                                 T *__restrict__ Y, GridParams gp)
 {
     int i, j, k;
     if (!grav_rep(gp, (long long)blockIdx.x * blockDim.x + threadIdx.x, i, j, k)) return;
@@ -336,7 +377,13 @@ __global__ void k_grav_butterfly(const T *__restrict__ X, T *__restrict__ Y, Gri
 #pragma unroll
             for (int mx = 0; mx < 2; mx++) {
                 const bool ok = (!mx || hx) && (!my || hy) && (!mz || hz);
-                a[mz][my][mx] = ok ? (double)X[((long long)cz[mz] * n1 + cy[my]) * n0 + cx[mx]] : 0.0;
+                double b = 0.0;
+                if (ok) {
+                    b = coef * (double)rho[((long long)cz[mz] * n1 + cy[my]) * n0 + cx[mx]];
+                    const long long e = grav_edge_index(cx[mx], cy[my], cz[mz], n0, n1, n2);
+                    if (e >= 0) b = b + (double)E[e];
+                }
+                a[mz][my][mx] = b;
             }
     grav_pairs(a);
     const int sx[2] = {i, grav_no(n0) + i}, sy[2] = {j, grav_no(n1) + j}, sz[2] = {k, grav_no(n2) + k};
@@ -384,8 +431,8 @@ __global__ void k_grav_unbutterfly(const T *__restrict__ Y, T *__restrict__ phi,
 }
 
 // Stage 3: amplitude / eigenvalue times the inverse transform's factor.
-// Grid: x over blockIdx.x, rows (j + n1 k, uniform per block) strided over
-// blockIdx.y.
+// Grid: x over blockIdx.x, groups of four rows (j + n1 k, uniform per
+// block) strided over blockIdx.y, the four loads in flight together.
 template <typename T>
 __global__ void k_grav_eigdiv(T *__restrict__ Y, const double *__restrict__ fx, const double *__restrict__ fy,
                               const double *__restrict__ fz, GridParams gp, double norm)
@@ -395,12 +442,29 @@ __global__ void k_grav_eigdiv(T *__restrict__ Y, const double *__restrict__ fx, 
     const int rows = n1 * gp.n[2];
     if (i >= n0) return;
     const double f0 = fx[i];
-    for (int row = blockIdx.y; row < rows; row += gridDim.y) {
-        const int k = row / n1, j = row - k * n1;
-        const long long c = (long long)row * n0 + i;
-        const double prod = f0 * fy[j] * fz[k];
-        const double lam = -6.0 * (1.0 - prod);
-        Y[c] = (T)((double)Y[c] / lam * norm);
+    constexpr int U = 4;  // rows in flight per thread
+    for (int rb = blockIdx.y * U; rb < rows; rb += gridDim.y * U) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) v[u] = rb + u < rows ? Y[(long long)(rb + u) * n0 + i] : T(0);
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int row = rb + u;
+            if (row >= rows) break;
+            const int k = row / n1, j = row - k * n1;
+            const double prod = f0 * fy[j] * fz[k];
+            const double lam = -6.0 * (1.0 - prod);
+#ifdef PPML_EXACT
+            Y[(long long)row * n0 + i] = (T)((double)v[u] / lam * norm);
+#else
+            // reciprocal by two Newton steps from the hardware estimate
+            // (within an ulp or two of the division)
+            double r = __builtin_amdgcn_rcp(lam);
+            r = r * (2.0 - lam * r);
+            r = r * (2.0 - lam * r);
+            Y[(long long)row * n0 + i] = (T)((double)v[u] * (r * norm));
+#endif
+        }
     }
 }
 
