@@ -341,8 +341,9 @@ def run_gravity(n=256, steps=50):
     import numpy as np
     import torch
 
+    from paper_1607_01105_amd import autotune
     from paper_1607_01105_amd import workloads as W
-    from paper_1607_01105_amd.ppml import Grid
+    from paper_1607_01105_amd.ppml import Grid, ppml_tile_shape
 
     prob = W.gravity_sphere(n, noise=0.01, seed=0)
     cells = prob.cells
@@ -352,7 +353,8 @@ def run_gravity(n=256, steps=50):
                        f"p = 0.05, outflow, CFL 0.3, {steps} steps", "cells": cells, "steps": steps}
     rho = {}
     for prec in ("fp32", "fp64"):
-        g = Grid.from_problem(prob, prec=prec)
+        tile = autotune.tune_grid(prob, prec, steps=3, warmup=1)["tile"]
+        g = Grid.from_problem(prob, prec=prec, tile=tile)
         g.step(2)
         g.sync()
         t0 = torch.cuda.Event(enable_timing=True)
@@ -368,6 +370,7 @@ def run_gravity(n=256, steps=50):
         mg, me, ml, k = g.get_timing_split()
         peak = 157.3 if prec == "fp32" else 78.6
         out[prec] = {"zone_updates_per_s": cells * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+                     "tile": list(ppml_tile_shape(3, tile)),
                      "split_ms": {"gravity": mg / k, "euler": me / k, "lagr": ml / k},
                      "transforms": {"algorithmic_gemm_flop": gemm_flop, "achieved_TFLOPs_over_gravity_solve":
                                     gemm_flop / (mg / k * 1e-3) / 1e12, "mfma_peak_TFLOPs": peak}}
@@ -401,16 +404,19 @@ def run_galaxy(steps=20, sizes=((256, ("fp32", "fp64")), (512, ("fp32",)))):
     whole steps (potential solve + both stage kernels) and the split."""
     import torch
 
+    from paper_1607_01105_amd import autotune
     from paper_1607_01105_amd import workloads as W
-    from paper_1607_01105_amd.ppml import Grid
+    from paper_1607_01105_amd.ppml import Grid, ppml_tile_shape
 
-    out = {"workload": "isothermal self-gravitating disk (cs = 0.05, G = 1) in a logarithmic halo potential, "
+    out = {"workload": "isothermal self-gravitating disk (cs = 0.05, G = 1) in the paper's dark-matter halo "
+                       "(density rho0 / (1 + (r/r0)^2) out to rh = 49.1 r0, r0 = 0.05), "
                        f"box [-1/2,1/2]^3, outflow, CFL 0.2, {steps} steps"}
     for n, precs in sizes:
         prob = W.galaxy_disk(n)
         out[str(n)] = {}
         for prec in precs:
-            g = Grid.from_problem(prob, prec=prec)
+            tile = autotune.tune_grid(prob, prec, steps=3, warmup=1)["tile"]
+            g = Grid.from_problem(prob, prec=prec, tile=tile)
             g.step(2)
             g.sync()
             g.set_timing(steps)
@@ -423,6 +429,7 @@ def run_galaxy(steps=20, sizes=((256, ("fp32", "fp64")), (512, ("fp32",)))):
             ms = t0.elapsed_time(t1)
             mg, me, ml, k = g.get_timing_split()
             out[str(n)][prec] = {"zone_updates_per_s": prob.cells * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+                                 "tile": list(ppml_tile_shape(3, tile)),
                                  "split_ms": {"gravity": mg / k, "euler": me / k, "lagr": ml / k}}
             _log(f"[bench] galaxy {n}^3 {prec}: {ms / steps:.3f} ms/step (gravity {mg / k:.3f} ms)")
             del g

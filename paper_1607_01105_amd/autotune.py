@@ -31,7 +31,9 @@ def tune_grid(prob, prec="fp32", steps=8, warmup=2, log=None) -> dict:
     """Best tile shape for stepping this problem alone (solo launches).
 
     Returns {"tile": index, "shape": (tx, ty), "ms_per_step": {index: ms}}."""
-    key = ("grid", prob.ndim, tuple(prob.n[:prob.ndim]), prec)
+    # the workload's name as well: its force terms select other kernel
+    # instantiations than a plain grid of the same size
+    key = ("grid", prob.name, prob.ndim, tuple(prob.n[:prob.ndim]), prec)
     if key in _cache:
         return _cache[key]
     lib = load()
