@@ -181,7 +181,10 @@ int ppml_set_conserved(ppml_grid *g, const double *const *f, double rho_mean0, d
  * step tau = cfl * min_d h_d / (max|v| + max c) of the current state (maxima
  * taken separately, Sec. 2.1).  t_stop > 0: clip the step so the run ends at
  * t_stop; steps after that are no-ops.  Asynchronous: errors of the step
- * itself are reported by the next synchronizing call.
+ * itself are reported by the next synchronizing call.  Calls of 32 steps or
+ * more replay a HIP graph of 32 steps (captured once per grid on a private
+ * stream, launched on the grid's stream) unless per-step timing is on or
+ * the grid has self-gravity; the results are the same bits.
  * Errors: PPML_EINVAL (nsteps < 0), PPML_ESTATE (state never set), PPML_EHIP. */
 int ppml_step(ppml_grid *g, int32_t nsteps, double dt_fixed, double t_stop);
 

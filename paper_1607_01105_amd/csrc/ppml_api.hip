@@ -232,6 +232,9 @@ struct ppml_grid {
     double *fx, *fy, *fz, *gpart;
     double grav_coef;      // 4 pi G h^2
     double grav_norm;      // prod_a 2 / (n_a + 1)
+    // a captured chunk of STEP_GRAPH steps, replayed by long ppml_step calls
+    hipGraphExec_t sexec;
+    bool graph_off;        // capture failed once: launch eagerly
 };
 
 namespace {
@@ -626,6 +629,8 @@ int ppml_create(const ppml_desc *d, void *state_dev, void *scratch_dev, void *hi
         }
     }
     g->blas = nullptr;
+    g->sexec = nullptr;
+    g->graph_off = false;
     g->phi = g->wx = g->wy = g->sx = g->sy = g->sz = g->gedge = nullptr;
     g->fx = g->fy = g->fz = g->gpart = nullptr;
     if (d->self_gravity) {
@@ -780,6 +785,55 @@ int ppml_set_conserved(ppml_grid *g, const double *const *f, double rho_mean0, d
     return finish_set(g, t, rho_mean0);
 }
 
+namespace {
+
+// Steps per captured graph of a solo grid.  Every step reads its time step
+// and run limits from the control block, so one graph of STEP_GRAPH steps
+// serves any call; steps past the run's end are no-ops.
+constexpr int STEP_GRAPH = 32;
+
+// Capture STEP_GRAPH steps of the grid into g->sexec (once).  The launches
+// are captured on a private non-blocking stream (the grid's own stream may be
+// the null stream, which cannot be captured); the graph is then launched on
+// the grid's stream, in order with the rest of its work.  False if capture
+// fails; the caller then launches eagerly.
+bool step_graph(ppml_grid *g)
+{
+    if (g->sexec) return true;
+    if (g->graph_off) return false;
+    g->graph_off = true;  // until the capture below succeeds
+    hipStream_t cap = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    hipGraph_t gr = nullptr;
+    hipGraphExec_t ex = nullptr;
+    bool ok = false;
+    const hipStream_t own = g->stream;
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        g->stream = cap;
+        int rc = PPML_OK;
+        for (int s = 0; s < STEP_GRAPH && rc == PPML_OK; s++)
+            rc = g->d.prec == PPML_FP64 ? launch_step<double>(g, nullptr) : launch_step<float>(g, nullptr);
+        g->stream = own;
+        const hipError_t e = hipStreamEndCapture(cap, &gr);
+        ok = rc == PPML_OK && e == hipSuccess && gr && hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0) == hipSuccess;
+    }
+    if (gr) (void)hipGraphDestroy(gr);
+    (void)hipStreamDestroy(cap);
+    (void)hipGetLastError();
+    if (!ok) {
+        if (ex) (void)hipGraphExecDestroy(ex);
+        return false;
+    }
+    g->sexec = ex;
+    g->graph_off = false;
+    return true;
+}
+
+}  // namespace
+
 int ppml_step(ppml_grid *g, int32_t nsteps, double dt_fixed, double t_stop)
 {
     int rc = grid_ok(g);
@@ -790,7 +844,15 @@ int ppml_step(ppml_grid *g, int32_t nsteps, double dt_fixed, double t_stop)
     if (nsteps == 0) return PPML_OK;
     if (g->in_batch) return fail(PPML_ESTATE, "grid is stepped by its batch");
     k_set_run<<<1, 1, 0, g->stream>>>(g->ctrl, dt_fixed, t_stop, (long long)nsteps);
-    for (int s = 0; s < nsteps; s++) {
+    // long calls replay the captured chunk (launch overhead once per
+    // STEP_GRAPH steps); not while per-step timing is recorded, nor with
+    // self-gravity (its library GEMMs stay outside captured graphs)
+    const bool timing = (size_t)(4 * (g->timed + 1)) <= g->ev.size();
+    int s = 0;
+    if (nsteps >= STEP_GRAPH && !timing && !g->gp.self_grav && step_graph(g)) {
+        for (; s + STEP_GRAPH <= nsteps; s += STEP_GRAPH) HIPCHK(hipGraphLaunch(g->sexec, g->stream));
+    }
+    for (; s < nsteps; s++) {
         hipEvent_t *ev = nullptr;
         if ((size_t)(4 * (g->timed + 1)) <= g->ev.size()) ev = &g->ev[4 * g->timed];
         rc = g->d.prec == PPML_FP64 ? launch_step<double>(g, ev) : launch_step<float>(g, ev);
@@ -967,6 +1029,7 @@ int ppml_destroy(ppml_grid *g)
     if (g->in_batch) return fail(PPML_ESTATE, "retire the grid from its batch first");
     (void)hipStreamSynchronize(g->stream);
     for (hipEvent_t e : g->ev) (void)hipEventDestroy(e);
+    if (g->sexec) (void)hipGraphExecDestroy(g->sexec);
     if (g->blas) rocblas_destroy_handle(g->blas);
     delete g;
     return PPML_OK;
