@@ -96,6 +96,29 @@ __device__ __forceinline__ double dcopysign(double m, double s) { return __built
 __device__ __forceinline__ float dmin(float a, float b) { return __builtin_fminf(a, b); }
 __device__ __forceinline__ double dmin(double a, double b) { return __builtin_fmin(a, b); }
 
+// Reciprocal and reciprocal square root of a positive normal value for the
+// product build: FP32 the hardware estimates (about 1 ulp, as the build's
+// FP32 division and square root); FP64 the hardware estimate refined by two
+// Newton steps (within a few ulp; the correctly rounded FP64 division and
+// square root cost about three times as many instructions).
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fast_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double fast_rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    return r;
+}
+__device__ __forceinline__ double fast_rsqrt(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * __builtin_fma(-hx * y, y, 1.5);
+    y = y * __builtin_fma(-hx * y, y, 1.5);
+    return y;
+}
+
 // Index of the interior cell that supplies the value at index i (which may
 // lie in a ghost layer or, for cells of a partial tile, further out) along
 // an axis of n cells; flip = 1 when the wall-normal momentum changes sign.
@@ -306,13 +329,23 @@ __device__ __forceinline__ VP<T> riemann(T sa, T sb, T r32a, T r32b, T psa, T ps
     T A = r32a + r32b;
     T B = sa + sb;
     T C = psa + psb;
+#ifdef PPML_EXACT
     T lam = dsqrt(gamma * C / A);
     T Z = dsqrt(gamma * A * C) / B;
-#ifdef PPML_EXACT
     T z = lam * tau / h;
 #else
+    // the same quantities from three reciprocal estimates instead of three
+    // divisions and two square roots: q = lambda^2 = gamma C / A,
+    // lambda = q / sqrt(q), Z = sqrt(gamma A C) / B = A lambda / B, and
+    // 1 / Z = B / (A lambda)
     (void)tau;
     (void)h;
+    const T iA = fast_rcp(A);
+    const T q = gamma * C * iA;
+    const T rl = fast_rsqrt(q);
+    T lam = q * rl;
+    T Z = A * lam * fast_rcp(B);
+    const T iZ = B * iA * rl;
     T z = lam * tau_over_h;
 #endif
     T vm = avg_left(va.L, va.R, va.Q6, z);
@@ -320,7 +353,11 @@ __device__ __forceinline__ VP<T> riemann(T sa, T sb, T r32a, T r32b, T psa, T ps
     T pm = avg_left(pa.L, pa.R, pa.Q6, z);
     T pp = avg_right(pb.L, pb.R, pb.Q6, z);
     VP<T> o;
+#ifdef PPML_EXACT
     o.V = K<T>::half * (vm + vp) + (pm - pp) / (K<T>::two * Z);
+#else
+    o.V = K<T>::half * (vm + vp) + (pm - pp) * (K<T>::half * iZ);
+#endif
     o.P = K<T>::half * (pm + pp) + (K<T>::half * Z) * (vm - vp);
     return o;
 }
