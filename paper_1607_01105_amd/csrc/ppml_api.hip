@@ -802,9 +802,17 @@ bool step_graph(ppml_grid *g)
     if (g->sexec) return true;
     if (g->graph_off) return false;
     g->graph_off = true;  // until the capture below succeeds
+    // capture on the grid's device, whichever device is current
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != g->device && hipSetDevice(g->device) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
     hipStream_t cap = nullptr;
     if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
         (void)hipGetLastError();
+        if (prev >= 0 && prev != g->device) (void)hipSetDevice(prev);
         return false;
     }
     hipGraph_t gr = nullptr;
@@ -823,6 +831,7 @@ bool step_graph(ppml_grid *g)
     if (gr) (void)hipGraphDestroy(gr);
     (void)hipStreamDestroy(cap);
     (void)hipGetLastError();
+    if (prev >= 0 && prev != g->device) (void)hipSetDevice(prev);
     if (!ok) {
         if (ex) (void)hipGraphExecDestroy(ex);
         return false;
