@@ -373,7 +373,11 @@ template <typename T> __device__ __forceinline__ T upwind_flux(T vh, T z, const 
 // Density-weighted interface velocity (Sec. 2.3).
 template <typename T> __device__ __forceinline__ T interface_velocity(T va, T sa, T vb, T sb)
 {
+#ifdef PPML_EXACT
     return (va * sa + vb * sb) / (sa + sb);
+#else
+    return (va * sa + vb * sb) * fast_rcp(sa + sb);
+#endif
 }
 
 // Gradient of the fixed potential at a cell centre (eqs. (2)-(3) force terms).

@@ -94,12 +94,22 @@ __global__ void k_set_run(Ctrl *ctrl, double dt_fixed, double t_stop, long long 
 template <typename T, int NDIM>
 __device__ __forceinline__ void cell_speeds(T r, T mx, T my, T mz, T e, T prho, T gam, T gm1, T &v, T &c)
 {
+#ifdef PPML_EXACT
     T ux = mx / r;
     T uy = NDIM >= 2 ? my / r : T(0);
     T uz = NDIM >= 3 ? mz / r : T(0);
     v = dsqrt(ux * ux + uy * uy + uz * uz);
     T p = prho * r + gm1 * e;
     c = dsqrt(gam * p / r);
+#else
+    const T ir = fast_rcp(r);
+    T ux = mx * ir;
+    T uy = NDIM >= 2 ? my * ir : T(0);
+    T uz = NDIM >= 3 ? mz * ir : T(0);
+    v = dsqrt(ux * ux + uy * uy + uz * uz);
+    T p = prho * r + gm1 * e;
+    c = dsqrt(gam * p * ir);
+#endif
 }
 
 __device__ __forceinline__ void publish_max(Ctrl *ctrl, int slot, double v, double c)
@@ -351,7 +361,11 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
                     e = inflow_value<T>(ctrl, fzi, 5);
                 }
             }
+#ifdef PPML_EXACT
             const T vz = mzv / rho;
+#else
+            const T vz = mzv * fast_rcp(rho);
+#endif
             const T p = prho * rho + gm1 * e;
             const T s = dsqrt(rho);
             qv0 = qv1; qv1 = qv2; qv2 = vz;
@@ -406,7 +420,7 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
 #ifdef PPML_EXACT
             s_vx[li] = mxv / rho;
 #else
-            const T ir = T(1) / rho;
+            const T ir = fast_rcp(rho);
             s_vx[li] = mxv * ir;
 #endif
             if constexpr (NDIM >= 2) {
@@ -440,7 +454,7 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
 #ifdef PPML_EXACT
                 s_vx[li] = mxv / rho;
 #else
-                const T ir = T(1) / rho;
+                const T ir = fast_rcp(rho);
                 s_vx[li] = mxv * ir;
 #endif
                 if constexpr (NDIM >= 2) {
@@ -797,7 +811,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
 #ifdef PPML_EXACT
                 s_vx[slot][li] = mxv / rho;
 #else
-                const T ir = T(1) / rho;
+                const T ir = fast_rcp(rho);
                 s_vx[slot][li] = mxv * ir;
 #endif
                 if constexpr (NDIM >= 2) {
@@ -837,7 +851,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
 #ifdef PPML_EXACT
                     s_vx[slot][li] = mxv / rho;
 #else
-                    const T ir = T(1) / rho;
+                    const T ir = fast_rcp(rho);
                     s_vx[slot][li] = mxv * ir;
 #endif
                     if constexpr (NDIM >= 2) {
@@ -1222,7 +1236,11 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                     fn[NDIM + 2] = (T)Et;
                 }
             } else {
+#ifdef PPML_EXACT
                 const double kin = (mx * mx + my * my + mz * mz) / (2.0 * r);
+#else
+                const double kin = (mx * mx + my * my + mz * mz) * (0.5 * fast_rcp(r));
+#endif
                 const double d = Et - kin;
                 if (d > 0.0) fn[NDIM + 2] = (T)d;
             }
