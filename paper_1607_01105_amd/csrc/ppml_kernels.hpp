@@ -624,9 +624,12 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
     // the second of two tile buffers
     constexpr bool PIPE = sizeof(T) == 4 && NDIM == 3 && G >= NF;
     constexpr int NBUF = PIPE ? 2 : 1;
-    __shared__ T s_f[NBUF][G][PS];
-    __shared__ T s_qx[G][NXQ];
-    __shared__ T s_qy[G][NYQ > 0 ? NYQ : 1];
+    // field slots of the tiles: G per pass, or all NF fields when they are
+    // fewer (1-D and 2-D FP32), so that no slot of LDS goes unused
+    constexpr int GL = G < NF ? G : NF;
+    __shared__ T s_f[NBUF][GL][PS];
+    __shared__ T s_qx[GL][NXQ];
+    __shared__ T s_qy[GL][NYQ > 0 ? NYQ : 1];
     // fluxes reuse the interface-value arrays once those are consumed
     static_assert(NXI <= NXQ && NYI <= NYQ + 1, "flux arrays must fit in the face arrays");
     T (*s_Fx)[NXQ] = s_qx;
