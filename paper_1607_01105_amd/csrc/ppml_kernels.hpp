@@ -223,12 +223,13 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
 
     // The velocity and pressure tiles (read by the parabola jobs) and the
     // interface states (written by the Riemann jobs, read by the update) are
-    // never live at once.  FP64 overlays them where that lets three waves
-    // per SIMD fit the CU's 160 KiB of LDS and keeping them apart does not
-    // (16x16: 59.6 -> 50.9 KB), at the price of one barrier per plane before
-    // the tiles are rewritten.  LDS is taken as granted in 2 KiB steps: a
-    // 4-wave group of 53.9 KB measured two resident groups per CU, not
-    // three.  FP32 tiles are small enough already.
+    // never live at once.  FP64 3-D overlays them where that lets three
+    // waves per SIMD fit the CU's 160 KiB of LDS and keeping them apart does
+    // not (16x16: 59.6 -> 50.9 KB), at the price of one barrier per plane
+    // before the tiles are rewritten.  LDS is taken as granted in 2 KiB
+    // steps: a 4-wave group of 53.9 KB measured two resident groups per CU,
+    // not three.  FP32 3-D groups are held to four per CU by their
+    // registers already.
     constexpr int NVY = NDIM >= 2 ? PS : 1;
     constexpr size_t B_TILE = ((size_t)(2 * PS + NVY) * sizeof(T) + 15) & ~(size_t)15;
     constexpr size_t B_IFACE = (size_t)(NXI + NYI) * sizeof(VP<T>);
@@ -236,7 +237,13 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
     constexpr size_t GROUPS3 = NT >= 64 ? (size_t)12 / (NT / 64) : 12;  // groups per CU for 3 waves/SIMD
     constexpr size_t B_SEP = (B_TILE + B_IFACE + B_REST + 2047) & ~(size_t)2047;
     constexpr size_t B_OVL = ((B_TILE > B_IFACE ? B_TILE : B_IFACE) + B_REST + 2047) & ~(size_t)2047;
-    constexpr bool OVERLAY = sizeof(T) == 8 && GROUPS3 * B_OVL <= 163840 && GROUPS3 * B_SEP > 163840;
+    // 1-D and 2-D kernels hold few registers, so LDS alone decides how many
+    // groups fit (up to 32 waves per CU): overlay where that adds a group
+    constexpr size_t GMAX = NT >= 64 ? (size_t)32 / (NT / 64) : 32;
+    constexpr size_t G_SEP = 163840 / B_SEP < GMAX ? 163840 / B_SEP : GMAX;
+    constexpr size_t G_OVL = 163840 / B_OVL < GMAX ? 163840 / B_OVL : GMAX;
+    constexpr bool OVERLAY = (sizeof(T) == 8 && GROUPS3 * B_OVL <= 163840 && GROUPS3 * B_SEP > 163840) ||
+                             (NDIM <= 2 && G_OVL > G_SEP);
     constexpr size_t B_UNION = OVERLAY ? (B_TILE > B_IFACE ? B_TILE : B_IFACE) : B_TILE + B_IFACE;
     __shared__ __align__(16) unsigned char s_union[B_UNION];
     T *const s_vx = reinterpret_cast<T *>(s_union);
