@@ -745,7 +745,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
     }
     T sz0 = 1, sz1 = 1, sz2 = 1, sz3 = 1;  // sqrt(rho) of the column at m-3..m
     T vtz_prev = 0;                        // transverse velocity of the column at m-3
-    double vmax = 0.0, cmax = 0.0;
+    T vmax = T(0), cmax = T(0);  // running maxima (FP64 only once published)
 
     const int m_beg = NDIM == 3 ? z0 - 3 : 0;
     const int m_end = NDIM == 3 ? z1 + 3 : 1;
@@ -1260,13 +1260,13 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
             cell_speeds<T, NDIM>(fn[0], fn[1], NDIM >= 2 ? fn[2] : T(0), NDIM >= 3 ? fn[3] : T(0), fn[NDIM + 2], prho,
                                  gam, gm1, v, cs);
             const bool bad = !(fn[0] > T(0)) || !(fn[NDIM + 2] > T(0)) || !(v == v) || !(cs == cs) ||
-                             __builtin_isinf((double)v) || __builtin_isinf((double)fn[NDIM + 1]);
+                             __builtin_isinf(v) || __builtin_isinf(fn[NDIM + 1]);
             if (bad) atomicOr(&ctrl->err, 1);
-            vmax = vmax > (double)v ? vmax : (double)v;
-            cmax = cmax > (double)cs ? cmax : (double)cs;
+            vmax = vmax > v ? vmax : v;
+            cmax = cmax > cs ? cmax : cs;
         }
     }
-    publish_max(ctrl, sl ^ 1, vmax, cmax);
+    publish_max(ctrl, sl ^ 1, (double)vmax, (double)cmax);
 }
 
 // Waves per SIMD the register allocator aims for in the Lagrangian kernel:
