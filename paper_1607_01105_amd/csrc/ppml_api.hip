@@ -853,6 +853,7 @@ int ppml_step(ppml_grid *g, int32_t nsteps, double dt_fixed, double t_stop)
     if (nsteps == 0) return PPML_OK;
     if (g->in_batch) return fail(PPML_ESTATE, "grid is stepped by its batch");
     k_set_run<<<1, 1, 0, g->stream>>>(g->ctrl, dt_fixed, t_stop, (long long)nsteps);
+    HIPCHK(hipGetLastError());  // before a capture attempt clears the last error
     // long calls replay the captured chunk (launch overhead once per
     // STEP_GRAPH steps); not while per-step timing is recorded, nor with
     // self-gravity (its library GEMMs stay outside captured graphs)
