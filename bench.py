@@ -300,11 +300,13 @@ def run_suite():
     """The paper's test-suite workloads at their full sizes, each run to its
     stop time with CFL steps (host-driven chunks of 64 steps): two blast
     waves (1-D, 2400 cells, FP64, t = 0.038), Sedov (100^3, t = 0.05) and
-    Kelvin-Helmholtz (256^2, t = 1) in FP32 and FP64."""
+    Kelvin-Helmholtz (256^2, t = 1) in FP32 and FP64; tile shapes from the
+    autotuner."""
     import torch
 
+    from paper_1607_01105_amd import autotune
     from paper_1607_01105_amd import workloads as W
-    from paper_1607_01105_amd.ppml import Grid
+    from paper_1607_01105_amd.ppml import Grid, ppml_tile_shape
 
     out = {}
     for name, prob, precs in (("blast_waves_2400", W.blast_waves(), ("fp64",)),
@@ -312,12 +314,14 @@ def run_suite():
                               ("kelvin_helmholtz_256", W.kelvin_helmholtz(256), ("fp32", "fp64"))):
         out[name] = {}
         for prec in precs:
-            g = Grid.from_problem(prob, prec=prec)
+            tile = autotune.tune_grid(prob, prec, steps=8, warmup=2)["tile"]
+            g = Grid.from_problem(prob, prec=prec, tile=tile)
             g.sync()
             t0 = time.perf_counter()
             t, _, n = g.run_to(prob.t_stop)
             sec = time.perf_counter() - t0
-            out[name][prec] = {"steps": n, "t": t, "zone_updates_per_s": prob.cells * n / sec, "seconds": sec}
+            out[name][prec] = {"steps": n, "t": t, "zone_updates_per_s": prob.cells * n / sec, "seconds": sec,
+                               "tile": list(ppml_tile_shape(prob.ndim, tile))}
             del g
         torch.cuda.empty_cache()
     return out
