@@ -27,7 +27,7 @@ BASE_FLAGS = [
 ]
 
 
-def build_one(out: str, exact: bool) -> str:
+def _command(out: str, exact: bool) -> list[str]:
     flags = list(BASE_FLAGS)
     if exact:
         flags += ["-DPPML_EXACT=1", "-ffp-contract=off"]
@@ -38,19 +38,34 @@ def build_one(out: str, exact: bool) -> str:
         # 1e-38); FP64 keeps correctly rounded division, square root and
         # subnormals
         flags += ["-fno-hip-fp32-correctly-rounded-divide-sqrt", "-fgpu-flush-denormals-to-zero"]
-    tmp = out + ".tmp"
     # rocBLAS runs the GEMMs of the self-gravity sine transforms
-    cmd = [HIPCC, *flags, SRC, "-o", tmp, "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
-    r = subprocess.run(cmd, capture_output=True, text=True)
+    return [HIPCC, *flags, SRC, "-o", out + ".tmp", "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+
+
+def build_one(out: str, exact: bool) -> str:
+    r = subprocess.run(_command(out, exact), capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError(f"hipcc failed for {out}")
-    os.replace(tmp, out)
+    os.replace(out + ".tmp", out)
     return out
 
 
 def build() -> list[str]:
-    return [build_one(LIB, False), build_one(LIB_EXACT, True)]
+    """Both libraries, compiled side by side."""
+    jobs = [(out, subprocess.Popen(_command(out, exact), stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True))
+            for out, exact in ((LIB, False), (LIB_EXACT, True))]
+    failed = []
+    for out, proc in jobs:
+        log, _ = proc.communicate()
+        if proc.returncode != 0:
+            sys.stderr.write(log)
+            failed.append(out)
+    if failed:
+        raise RuntimeError(f"hipcc failed for {', '.join(failed)}")
+    for out, _ in jobs:
+        os.replace(out + ".tmp", out)
+    return [out for out, _ in jobs]
 
 
 if __name__ == "__main__":
