@@ -291,6 +291,37 @@ int ppml_batch_set_tile(ppml_batch *b, int32_t ndim, int32_t variant);
 /* Destroy the batch (admitted grids become free-standing again). */
 int ppml_batch_destroy(ppml_batch *b);
 
+/* ---- Allocation-free stepping -------------------------------------------
+ * For callers that cannot allocate memory: code under HIP graph capture
+ * (with t_out and steps_out NULL), tight serving loops, harnesses that forbid
+ * hipMalloc.  One call does what ppml_create on state_dev, ppml_set_conserved
+ * of the state already on the device, ppml_step and ppml_get_time do, with
+ * the same kernels and the same results, but allocates nothing: no device or
+ * host memory, no host object, no graph.  The grid's work area (the
+ * Eulerian-stage output, the control block and the totals partials: the
+ * ppml_scratch_bytes of the descriptor) lies in a fixed area inside the
+ * library, PPML_NOALLOC_SCRATCH_BYTES per GPU, held from the first call on
+ * that GPU until the process ends.
+ *   state_dev: the conserved state in the layout above (ppml_state_bytes,
+ *              256-byte aligned), caller-owned, advanced in place;
+ *   rho_mean0: vacuum reference density (Sec. 2.4); <= 0: the mean of the
+ *              state's density;
+ *   t0:        time of the state; nsteps, dt_fixed, t_stop as in ppml_step
+ *              (steps launched one by one on hip_stream);
+ *   t_out, steps_out: when either is non-NULL the call synchronizes the
+ *              stream and returns the time and the number of steps taken
+ *              (PPML_ENONFINITE if a step produced a non-physical state);
+ *              when both are NULL it only enqueues.
+ * Every call on a GPU shares that GPU's work area, which keeps the last
+ * call's contents (each call starts by rewriting everything it reads), so
+ * calls that overlap on one GPU (other streams or threads) race: the caller
+ * serializes them.  Errors: PPML_EINVAL (descriptor, self-gravity, a work
+ * area above PPML_NOALLOC_SCRATCH_BYTES, NULL or misaligned state, nsteps < 0,
+ * non-finite arguments), PPML_EHIP, PPML_ENONFINITE. */
+#define PPML_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int ppml_step_noalloc(const ppml_desc *d, void *state_dev, double rho_mean0, double t0, int32_t nsteps,
+                      double dt_fixed, double t_stop, void *hip_stream, double *t_out, int64_t *steps_out);
+
 /* Library version (major*10000 + minor*100 + patch). */
 int ppml_version(void);
 

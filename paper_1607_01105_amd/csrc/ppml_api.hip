@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -425,11 +426,13 @@ int settle(ppml_grid *g)
     return PPML_OK;
 }
 
-// After the state is set: reset the control block, record the mean density,
-// compute the CFL maxima of the state into slot 0.
-int finish_set(ppml_grid *g, double t, double rho_mean0)
+// After the state is set: reset the control block, record the mean density
+// (the given one, or the mean of the state when rho_mean0 <= 0), compute the
+// CFL maxima of the state into slot 0.  Kernels only: nothing is copied from
+// the host.
+int finish_set_async(ppml_grid *g, double t, double rho_mean0)
 {
-    k_ctrl_reset<<<1, 1, 0, g->stream>>>(g->ctrl, t);
+    k_ctrl_reset<<<1, 1, 0, g->stream>>>(g->ctrl, t, rho_mean0);
     HIPCHK(hipGetLastError());
     if (g->d.prec == PPML_FP64) {
         launch_totals<double>(g, rho_mean0 > 0.0 ? 0.0 : (double)g->gp.ncell);
@@ -439,10 +442,15 @@ int finish_set(ppml_grid *g, double t, double rho_mean0)
         launch_speeds<float>(g);
     }
     HIPCHK(hipGetLastError());
-    if (rho_mean0 > 0.0)
-        HIPCHK(hipMemcpyAsync(&g->ctrl->rho_mean0, &rho_mean0, sizeof(double), hipMemcpyHostToDevice, g->stream));
-    HIPCHK(hipStreamSynchronize(g->stream));
     g->has_state = true;
+    return PPML_OK;
+}
+
+int finish_set(ppml_grid *g, double t, double rho_mean0)
+{
+    int rc = finish_set_async(g, t, rho_mean0);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(g->stream));
     return PPML_OK;
 }
 
@@ -547,16 +555,15 @@ size_t ppml_scratch_bytes(const ppml_desc *d)
     return layout(d).total;
 }
 
-int ppml_create(const ppml_desc *d, void *state_dev, void *scratch_dev, void *hip_stream, ppml_grid **out)
+}  // extern "C"
+
+namespace {
+
+// Grid parameters, pointers into the scratch area and the inflow ghost states
+// of a validated descriptor (everything of ppml_create but the self-gravity
+// set-up and the z chunks).  Allocates nothing: g is the caller's object.
+int init_grid(ppml_grid *g, const ppml_desc *d, void *state_dev, void *scratch_dev, void *hip_stream)
 {
-    int rc = validate(d);
-    if (rc != PPML_OK) return rc;
-    if (!out) return fail(PPML_EINVAL, "out is NULL");
-    if (!state_dev || !scratch_dev) return fail(PPML_EINVAL, "state and scratch pointers must be non-NULL");
-    if (((uintptr_t)state_dev % ALIGN) || ((uintptr_t)scratch_dev % ALIGN))
-        return fail(PPML_EINVAL, "device pointers must be %zu-byte aligned", ALIGN);
-    ppml_grid *g = new (std::nothrow) ppml_grid();
-    if (!g) return fail(PPML_ENOMEM, "host allocation failed");
     g->d = *d;
     HIPCHK(hipGetDevice(&g->device));
     g->stream = (hipStream_t)hip_stream;
@@ -622,17 +629,65 @@ int ppml_create(const ppml_desc *d, void *state_dev, void *scratch_dev, void *hi
             gp.any_inflow = 1;
         }
     if (gp.any_inflow) {
-        hipError_t e = hipMemcpy((char *)g->ctrl + offsetof(Ctrl, inflow), tab, sizeof tab, hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            delete g;
-            return fail(PPML_EHIP, "inflow states: %s", hipGetErrorString(e));
-        }
+        InflowTable it;
+        memcpy(it.v, tab, sizeof tab);
+        k_set_inflow<<<1, 64, 0, g->stream>>>(g->ctrl, it);
+        HIPCHK(hipGetLastError());
     }
     g->blas = nullptr;
     g->sexec = nullptr;
     g->graph_off = false;
     g->phi = g->wx = g->wy = g->sx = g->sy = g->sz = g->gedge = nullptr;
     g->fx = g->fy = g->fz = g->gpart = nullptr;
+    g->has_state = false;
+    g->in_batch = false;
+    g->bstream = nullptr;
+    g->timed = 0;
+    return PPML_OK;
+}
+
+// Z chunks of the solo stage launches, fitted to the resident work groups of
+// each stage kernel (start-up cost: 3 z-only planes in the Eulerian kernel, 6
+// in the Lagrangian kernel).  After the self-gravity set-up, which selects
+// the Eulerian instantiation.
+void init_chunks(ppml_grid *g)
+{
+    const GridParams &gp = g->gp;
+    const ppml_desc *d = &g->d;
+    g->gpE = gp;
+    g->gpL = gp;
+    if (d->ndim == 3) {
+        long long se, sl;
+        const int xf = gp.potential == POT_HALO ? 2 : (gp.self_grav ? 1 : 0);
+        if (d->prec == PPML_FP64) stage_slots<double>(g->device, d->tile, xf, se, sl);
+        else stage_slots<float>(g->device, d->tile, xf, se, sl);
+        const long long txy = (long long)gp.tiles[0] * gp.tiles[1];
+        set_chunks(g->gpE, choose_chunks(txy, gp.n[2], se, 1.5));
+        set_chunks(g->gpL, choose_chunks(txy, gp.n[2], sl, 3.0));
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int ppml_create(const ppml_desc *d, void *state_dev, void *scratch_dev, void *hip_stream, ppml_grid **out)
+{
+    int rc = validate(d);
+    if (rc != PPML_OK) return rc;
+    if (!out) return fail(PPML_EINVAL, "out is NULL");
+    if (!state_dev || !scratch_dev) return fail(PPML_EINVAL, "state and scratch pointers must be non-NULL");
+    if (((uintptr_t)state_dev % ALIGN) || ((uintptr_t)scratch_dev % ALIGN))
+        return fail(PPML_EINVAL, "device pointers must be %zu-byte aligned", ALIGN);
+    ppml_grid *g = new (std::nothrow) ppml_grid();
+    if (!g) return fail(PPML_ENOMEM, "host allocation failed");
+    if ((rc = init_grid(g, d, state_dev, scratch_dev, hip_stream))) {
+        delete g;
+        return rc;
+    }
+    GridParams &gp = g->gp;
+    const ScratchLayout L = layout(d);
+    char *s = (char *)scratch_dev;
     if (d->self_gravity) {
         g->phi = s + L.phi;
         g->wx = s + L.wx;
@@ -675,23 +730,7 @@ int ppml_create(const ppml_desc *d, void *state_dev, void *scratch_dev, void *hi
             return fail(PPML_EHIP, "self-gravity tables: %s", hipGetErrorString(e));
         }
     }
-    g->gpE = gp;
-    g->gpL = gp;
-    if (d->ndim == 3) {
-        // solo launches: z chunks fitted to the resident work groups of each
-        // stage kernel (start-up cost: 3 z-only planes in the Eulerian
-        // kernel, 6 in the Lagrangian kernel)
-        long long se, sl;
-        const int xf = gp.potential == POT_HALO ? 2 : (gp.self_grav ? 1 : 0);
-        if (d->prec == PPML_FP64) stage_slots<double>(g->device, d->tile, xf, se, sl);
-        else stage_slots<float>(g->device, d->tile, xf, se, sl);
-        const long long txy = (long long)gp.tiles[0] * gp.tiles[1];
-        set_chunks(g->gpE, choose_chunks(txy, gp.n[2], se, 1.5));
-        set_chunks(g->gpL, choose_chunks(txy, gp.n[2], sl, 3.0));
-    }
-    g->has_state = false;
-    g->in_batch = false;
-    g->timed = 0;
+    init_chunks(g);
     *out = g;
     return PPML_OK;
 }
@@ -870,6 +909,89 @@ int ppml_step(ppml_grid *g, int32_t nsteps, double dt_fixed, double t_stop)
         if (ev) g->timed++;
     }
     HIPCHK(hipGetLastError());
+    return PPML_OK;
+}
+
+}  // extern "C"
+
+// Work area of ppml_step_noalloc: the Eulerian-stage output, the control block
+// and the totals partials of one grid, one copy per GPU the library runs on,
+// held until the process ends.  Host code never passes the array's name to a
+// kernel or a copy (in host code it is only a stand-in for the device
+// symbol): its device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[PPML_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEV = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[NOALLOC_MAX_DEV];
+
+// Device address of the work area on the current device (looked up on the
+// first call on that device, with the device current).
+int noalloc_area(int device, void **out)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEV) return fail(PPML_EINVAL, "device %d out of range", device);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(PPML_EHIP, "hipGetSymbolAddress of the work area: %s", hipGetErrorString(e));
+        g_noalloc_ptr[device] = ptr;
+    }
+    *out = g_noalloc_ptr[device];
+    return PPML_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ppml_step_noalloc(const ppml_desc *d, void *state_dev, double rho_mean0, double t0, int32_t nsteps,
+                      double dt_fixed, double t_stop, void *hip_stream, double *t_out, int64_t *steps_out)
+{
+    int rc = validate(d);
+    if (rc != PPML_OK) return rc;
+    if (d->self_gravity) return fail(PPML_EINVAL, "self-gravity grids step through ppml_create / ppml_step");
+    if (!state_dev) return fail(PPML_EINVAL, "state pointer must be non-NULL");
+    if ((uintptr_t)state_dev % ALIGN) return fail(PPML_EINVAL, "the state pointer must be %zu-byte aligned", ALIGN);
+    if (nsteps < 0) return fail(PPML_EINVAL, "nsteps must be >= 0");
+    if (!std::isfinite(dt_fixed) || !std::isfinite(t_stop) || !std::isfinite(rho_mean0))
+        return fail(PPML_EINVAL, "dt_fixed, t_stop and rho_mean0 must be finite");
+    if (!std::isfinite(t0) || t0 < 0.0) return fail(PPML_EINVAL, "t0 must be finite and >= 0");
+    const size_t need = layout(d).total;
+    if (need > (size_t)PPML_NOALLOC_SCRATCH_BYTES)
+        return fail(PPML_EINVAL, "the grid needs %zu bytes of work area; the fixed area holds %zu", need,
+                    (size_t)PPML_NOALLOC_SCRATCH_BYTES);
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    void *area = nullptr;
+    if ((rc = noalloc_area(dev, &area))) return rc;
+    ppml_grid g{};  // on the stack: no host allocation
+    if ((rc = init_grid(&g, d, state_dev, area, hip_stream))) return rc;
+    init_chunks(&g);
+    // every value of the work area that a step reads is written first: the
+    // control block by the reset, the maxima slots, the mean density and the
+    // partials by the kernels below, the stage output by the Eulerian kernel
+    if ((rc = finish_set_async(&g, t0, rho_mean0))) return rc;
+    if (nsteps > 0) {
+        k_set_run<<<1, 1, 0, g.stream>>>(g.ctrl, dt_fixed, t_stop, (long long)nsteps);
+        HIPCHK(hipGetLastError());
+        for (int s = 0; s < nsteps; s++) {
+            rc = d->prec == PPML_FP64 ? launch_step<double>(&g, nullptr) : launch_step<float>(&g, nullptr);
+            if (rc) return rc;
+        }
+    }
+    HIPCHK(hipGetLastError());
+    if (t_out || steps_out) {
+        Ctrl c;
+        HIPCHK(hipMemcpyAsync(&c, g.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, g.stream));
+        HIPCHK(hipStreamSynchronize(g.stream));
+        if (t_out) *t_out = c.t;
+        if (steps_out) *steps_out = c.steps;
+        if (c.err) return fail(PPML_ENONFINITE, "a step produced rho <= 0, eps <= 0 or a non-finite value");
+    }
     return PPML_OK;
 }
 

@@ -66,9 +66,12 @@ template <typename T> __global__ void k_to_double(const T *__restrict__ src, dou
         dst[c] = (double)src[c];
 }
 
-__global__ void k_ctrl_reset(Ctrl *ctrl, double t)
+// Control block of a freshly set state: time t, vacuum reference density
+// rho_mean0 (<= 0: left for the totals kernel to fill in).
+__global__ void k_ctrl_reset(Ctrl *ctrl, double t, double rho_mean0)
 {
     ctrl->t = t;
+    ctrl->rho_mean0 = rho_mean0 > 0.0 ? rho_mean0 : 0.0;
     ctrl->tau = 0.0;
     ctrl->dt_last = 0.0;
     ctrl->vmax_bits[0] = ctrl->vmax_bits[1] = 0ull;
@@ -80,6 +83,17 @@ __global__ void k_ctrl_reset(Ctrl *ctrl, double t)
     ctrl->err = 0;
     ctrl->slot_cur = 0;
     ctrl->slot_l = 0;
+}
+
+// Conserved ghost states of the inflow faces into the control block (set
+// once per grid; by value, so that no host buffer is involved).
+struct InflowTable {
+    double v[6][6];
+};
+__global__ void k_set_inflow(Ctrl *ctrl, InflowTable tab)
+{
+    const int i = threadIdx.x;
+    if (i < 36) ctrl->inflow[i / 6][i % 6] = tab.v[i / 6][i % 6];
 }
 
 // Parameters of the next run of steps of one grid.

@@ -53,7 +53,7 @@ EXPORTS = (
     "ppml_destroy", "ppml_strerror", "ppml_last_error", "ppml_version", "ppml_set_timing", "ppml_get_timing",
     "ppml_batch_create", "ppml_batch_admit", "ppml_batch_retire", "ppml_batch_step", "ppml_batch_sync",
     "ppml_batch_info", "ppml_batch_destroy", "ppml_tile_count", "ppml_tile_shape", "ppml_batch_set_tile",
-    "ppml_get_potential", "ppml_get_timing_split",
+    "ppml_get_potential", "ppml_get_timing_split", "ppml_step_noalloc",
 )
 
 _libs: dict[str, C.CDLL] = {}
@@ -100,6 +100,8 @@ def load(path: str | None = None) -> C.CDLL:
     lib.ppml_tile_count.argtypes = [C.c_int32]
     lib.ppml_tile_shape.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     lib.ppml_batch_set_tile.argtypes = [vp, C.c_int32, C.c_int32]
+    lib.ppml_step_noalloc.argtypes = [D, vp, C.c_double, C.c_double, C.c_int32, C.c_double, C.c_double, vp, dp,
+                                      C.POINTER(C.c_int64)]
     lib.ppml_strerror.restype = C.c_char_p
     lib.ppml_strerror.argtypes = [C.c_int]
     lib.ppml_last_error.restype = C.c_char_p
@@ -173,6 +175,18 @@ def ppml_create(desc, state_ptr: int, scratch_ptr: int, stream: int, lib=None):
     _check(lib, lib.ppml_create(C.byref(desc), C.c_void_p(state_ptr), C.c_void_p(scratch_ptr),
                                 C.c_void_p(stream), C.byref(h)))
     return h
+
+
+def ppml_step_noalloc(desc, state_ptr: int, nsteps: int, rho_mean0=0.0, t0=0.0, dt_fixed=0.0, t_stop=0.0,
+                      stream: int = 0, sync=True, lib=None):
+    """Allocation-free stepping of a state already on the device (see the
+    header): returns (t, steps) when sync, else None."""
+    lib = lib or load()
+    t, n = C.c_double(), C.c_int64()
+    _check(lib, lib.ppml_step_noalloc(C.byref(desc), C.c_void_p(state_ptr), float(rho_mean0), float(t0), int(nsteps),
+                                      float(dt_fixed), float(t_stop), C.c_void_p(stream),
+                                      C.byref(t) if sync else None, C.byref(n) if sync else None))
+    return (t.value, n.value) if sync else None
 
 
 def ppml_tile_count(ndim, lib=None) -> int:
