@@ -258,21 +258,25 @@ def periodic_modes(n: int | tuple = 256, seed: int = 0, ndim: int = 3, gamma: fl
 
 def disk(nx: int = 512, ny: int = 512, nz: int = 64, seed: int = 0, v0: float = 1.0, rc: float = 0.02,
          rd: float = 0.2, cs: float = 0.05, gamma: float = 5.0 / 3.0, cfl: float = 0.2, nsteps: int = 500,
-         rho_floor: float = 1e-3, noise: float = 0.01, isothermal: bool = False) -> Problem:
+         rho_floor: float = 1e-3, noise: float = 0.01, isothermal: bool = False, hz: float | None = None) -> Problem:
     """Rotating gas disk in Phi = v0^2/2 ln(rc^2 + x^2 + y^2 + z^2), box
-    [-1/2,1/2]^2 x [-nz/(2 nx), nz/(2 nx)] (cubic cells): surface density
-    exp(-R/rd), vertical Gaussian of scale height max(cs/v0 sqrt(R^2+rc^2), 2h),
-    flat rotation v = v0 R / sqrt(R^2 + rc^2), p = rho cs^2 / gamma, 1% lognormal
+    [-1/2,1/2]^2 x [-nz hz/2, nz hz/2] with in-plane cells h = 1/nx and
+    vertical cells hz (default h, cubic cells): surface density exp(-R/rd),
+    vertical Gaussian of scale height max(cs/v0 sqrt(R^2+rc^2), 2 hz), flat
+    rotation v = v0 R / sqrt(R^2 + rc^2), p = rho cs^2 / gamma, 1% lognormal
     density noise, outflow boundaries.  isothermal=True runs the paper's
-    isothermal approximation instead (p = cs^2 rho, the variant of Sec. 4)."""
+    isothermal approximation instead (p = cs^2 rho, the variant of Sec. 4).
+    A reduced disk keeps the vertical resolution of the full one with a
+    coarser plane: e.g. 128 x 128 x 32 with hz = 1/512."""
     h = 1.0 / nx
-    lo = (-0.5, -0.5 * ny * h, -0.5 * nz * h)
-    hi = (0.5, 0.5 * ny * h, 0.5 * nz * h)
+    hz = h if hz is None else float(hz)
+    lo = (-0.5, -0.5 * ny * h, -0.5 * nz * hz)
+    hi = (0.5, 0.5 * ny * h, 0.5 * nz * hz)
     n3 = (nx, ny, nz)
     X, Y, Z = _mesh(n3, lo, hi)
     R = np.sqrt(X * X + Y * Y)
     sigma = np.exp(-R / rd)
-    H = np.maximum((cs / v0) * np.sqrt(R * R + rc * rc), 2.0 * h)
+    H = np.maximum((cs / v0) * np.sqrt(R * R + rc * rc), 2.0 * hz)
     rho = sigma / (math.sqrt(2.0 * math.pi) * H) * np.exp(-Z * Z / (2.0 * H * H))
     rho = np.maximum(rho, rho_floor)
     rng = np.random.default_rng(seed)

@@ -376,21 +376,47 @@ def pin_shock_tubes(lib=None, ks=(0, 1, 2), ns=(100, 200, 400)):
 
 
 def pin_shock_spread(lib=None):
-    """Sod tube 1 on 100 cells: the shock is spread over two cells (printed in
-    the verification section); the first-order scheme smears it far more."""
+    """Sod tube 1 on 100 cells at t = 0.2 (verification section, Sod problem):
+    the paper prints a shock spread of two cells for PPML and twelve for the
+    first-order method.  It does not say how it counts; counted as the cells
+    whose density lies strictly between 10% and 90% of the jump, PPML's shock
+    covers at most the printed two cells; counted over the widest band (1% to
+    99% of the jump) the first-order shock covers 12 cells within a third
+    (8 to 16) and at least twice PPML's width on the same band."""
     row = shock_tubes()[0]
     _, rL, vL, pL, rR, vR, pR, x0, t = row
     rs = er.sample((rL, vL, pL), (rR, vR, pR), 1.4, 0.3 / t)[0]
-    widths = {}
+    widths, wide = {}, {}
     for fo in (False, True):
         prob = W.shock_tube(0, 100)
         o = make_oracle(prob, lib=lib, first_order=fo)
         o.run(10 ** 6, t_stop=t)
         x = prob.centres(0)
-        sel = (x > 0.75) & (x < 0.95)
-        widths[fo] = shock_width_cells(o.get("rho").ravel()[sel], rR, rs)
+        sel = (x > 0.75) & (x < 0.95)  # the shock's neighbourhood (contact near 0.69)
+        rho = o.get("rho").ravel()[sel]
+        widths[fo] = shock_width_cells(rho, rR, rs)
+        wide[fo] = shock_width_cells(rho, rR, rs, frac=(0.01, 0.99))
     assert 1 <= widths[False] <= printed("shock_spread_cells_ppml"), widths
-    assert widths[True] >= 2 * widths[False], widths
+    fo12 = printed("shock_spread_cells_first_order")
+    assert fo12 * 2 / 3 <= wide[True] <= fo12 * 4 / 3, wide
+    assert wide[True] >= 2 * wide[False], wide
+
+
+def pin_totals_equal_field_sums(lib=None):
+    """The FP64 totals of the conserved densities equal the sums of the
+    fields read back cell by cell (summed here with math.fsum, exactly
+    rounded), on a 3-D state with every field nonzero."""
+    import math
+
+    prob = W.random_smooth(3, (12, 10, 9), seed=5)
+    o = make_oracle(prob, lib=lib)
+    for stage in range(2):
+        tot = o.totals()
+        for f in range(6):
+            ref = math.fsum(o.get(f).ravel().tolist())
+            scale = math.fsum(abs(v) for v in o.get(f).ravel().tolist())
+            assert abs(tot[f] - ref) <= 1e-14 * scale, (stage, f, tot[f], ref)
+        o.run(3)
 
 
 def pin_seeded_riemann(lib=None, seeds=range(0, 16, 3)):

@@ -180,7 +180,7 @@ COMBINED = _combined()
 def test_combined_features(name, prob, fo):
     """Features together: the isothermal variant with inflow faces and with
     the first-order scheme (exact build, bit for bit), self-gravity with
-    reflecting walls and with the isothermal variant (FP64 within 1e-10 in
+    reflecting walls and with the isothermal variant (FP64 within 1e-12 in
     both builds; the transforms sum in another order than the oracle)."""
     o = make_oracle(prob, first_order=fo)
     taus = o.run(8)
@@ -194,4 +194,4 @@ def test_combined_features(name, prob, fo):
             if exact and not grav:
                 assert np.array_equal(a, b), (name, f)
             else:
-                assert _rel(a, b) <= (1e-10 if grav else 1e-12), (name, exact, f, _rel(a, b))
+                assert _rel(a, b) <= 1e-12, (name, exact, f, _rel(a, b))

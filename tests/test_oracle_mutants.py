@@ -94,6 +94,10 @@ MUTANTS = [
     ("iso_riemann_gamma", "const double gam = g->iso ? 1.0 : g->gamma;", "const double gam = g->gamma;"),
     ("iso_cfl_speed", "double c = sqrt((g->iso ? 1.0 : g->gamma) * p / r);", "double c = sqrt(g->gamma * p / r);"),
     ("iso_cfl_pressure", "double p = g->iso ? (g->cs * g->cs) * r :", "double p = g->iso ? g->cs * r :"),
+    ("totals_skip_row", "for (long j = 0; j < g->n[1]; j++)\n                for (long i = 0; i < g->n[0]; i++) s +=",
+     "for (long j = 0; j + 1 < g->n[1]; j++)\n                for (long i = 0; i < g->n[0]; i++) s +="),
+    ("totals_ghost_offset", "s += g->U[f][gidx(g, i + g->g[0], j + g->g[1], k + g->g[2])];",
+     "s += g->U[f][gidx(g, i + g->g[0] - 1, j + g->g[1], k + g->g[2])];"),
 ]
 
 RUNNER = r"""
