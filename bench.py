@@ -33,8 +33,10 @@ HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
+WORKLOAD_STEPS = 100
 WORKLOAD = ("3D 256^3 periodic unit cube, gamma 5/3, rho = 1 + 0.1 * 8 random modes (|k| <= 4), "
-            "p = 1 with p = 100 sphere r = 0.1 at centre, u = 0, CFL 0.3, 100 steps")
+            f"p = 1 with p = 100 sphere r = 0.1 at centre, u = 0, CFL 0.3; a {WORKLOAD_STEPS}-step run "
+            "(its first `steps` steps timed; accuracy after all of it)")
 
 
 # Algorithmic floating-point operations per zone of each 3-D stage kernel,
@@ -174,35 +176,47 @@ def run_batched(seed=0, steps=200, tune=True):
             "tile_shapes": {str(nd): list(r["shape"]) for nd, r in tuned.items()}}
 
 
-def run_served(n_requests=60, load=0.5, seed=0, budget_gib=4.0, round_steps=50, capacity_zu_per_s=None):
+def run_served(n_requests=400, loads=(0.5, 0.8), seed=0, budget_gib=4.0, round_steps=50, capacity_requests=150):
     """Served configuration: Poisson arrivals of 2-D (64^2-512^2) and 3-D
     (64^3-192^3) periodic boxes with a high-pressure sphere, 50-500 steps,
-    FP32, admitted by an HBM budget; rate = load x the saturated capacity
-    (the headline throughput divided by the mean work per request)."""
+    FP32, admitted by an HBM budget.  The server's saturated throughput is
+    measured first (every request of a trace of another seed present at time
+    zero); then n_requests arrive at each load x that capacity (divided by
+    the mean work per request) and p50/p99 completion latency is reported."""
     import numpy as np
 
-    from paper_1607_01105_amd import workloads as W
-    from paper_1607_01105_amd.serve import Server
-
-    probe = W.served_trace(seed, 4000, 1.0)
-    mean_zu = float(np.mean([r.cells * r.steps for r in probe]))
-    cap_rps = capacity_zu_per_s / mean_zu
-    rate = load * cap_rps
-    trace = W.served_trace(seed, n_requests, rate)
-    # tile shapes for the mix, tuned on a few requests of another seed
     from paper_1607_01105_amd import autotune
+    from paper_1607_01105_amd import workloads as W
+    from paper_1607_01105_amd.serve import Server, measure_capacity
 
+    budget = int(budget_gib * (1 << 30))
+    # tile shapes for the mix, tuned on a few requests of another seed
     sample = [r.problem() for r in W.served_trace(seed + 1, 6, 1.0, n2_range=(64, 256), n3_range=(64, 96))]
     tiles = {nd: r["tile"] for nd, r in autotune.tune_batch(sample, prec="fp32", steps=4, log=_log).items()}
-    srv = Server(budget_bytes=int(budget_gib * (1 << 30)), capacity=256, prec="fp32", round_steps=round_steps,
-                 tiles=tiles)
-    st = srv.run(trace)
-    return {"workload": "Poisson arrivals, 50% 2-D 64^2-512^2 / 50% 3-D 64^3-192^3 periodic boxes with one "
-                        "p=100 sphere, 50-500 steps, FP32", "requests": st["requests"], "rate_per_s": rate,
-            "load_vs_capacity": load, "budget_GiB": budget_gib, "round_steps": round_steps,
-            "latency_p50_s": st["latency_p50_s"], "latency_p99_s": st["latency_p99_s"],
+    cap = measure_capacity(capacity_requests, seed=seed + 1000, budget_bytes=budget, round_steps=round_steps,
+                           tiles=tiles)
+    _log(f"[bench] served saturation: {cap:.3e} zone-updates/s over {capacity_requests} requests")
+    probe = W.served_trace(seed, 4000, 1.0)
+    mean_zu = float(np.mean([r.cells * r.steps for r in probe]))
+    out = {"workload": "Poisson arrivals, 50% 2-D 64^2-512^2 / 50% 3-D 64^3-192^3 periodic boxes with one "
+                       "p=100 sphere, 50-500 steps, FP32",
+           "budget_GiB": budget_gib, "round_steps": round_steps, "tiles": {str(a): v for a, v in tiles.items()},
+           "saturated_zone_updates_per_s": cap, "saturation_requests": capacity_requests,
+           "mean_zone_updates_per_request": mean_zu, "loads": {}}
+    for load in loads:
+        rate = load * cap / mean_zu
+        trace = W.served_trace(seed, n_requests, rate)
+        srv = Server(budget_bytes=budget, capacity=256, prec="fp32", round_steps=round_steps, tiles=tiles,
+                     prep_workers=16, lookahead=64)
+        st = srv.run(trace)
+        _log(f"[bench] served load {load:.2f}: {st['requests']} requests at {rate:.2f}/s, p50 "
+             f"{st['latency_p50_s']:.3f} s, p99 {st['latency_p99_s']:.3f} s")
+        out["loads"][f"{load:.2f}"] = {
+            "requests": st["requests"], "rate_per_s": rate, "latency_p50_s": st["latency_p50_s"],
+            "latency_p99_s": st["latency_p99_s"], "latency_mean_s": st["latency_mean_s"],
             "zone_updates_per_s": st["zone_updates_per_s"], "rounds": st["rounds"],
-            "data_wait_mean_s": st["data_wait_mean_s"], "tiles": {str(a): v for a, v in tiles.items()}}
+            "data_wait_mean_s": st["data_wait_mean_s"]}
+    return out
 
 
 def run_disk(steps=500, isothermal=False):
@@ -236,21 +250,40 @@ def run_disk(steps=500, isothermal=False):
         del g
         torch.cuda.empty_cache()
     # accuracy at equal times (untimed): FP64 with its CFL steps, one at a
-    # time to record them, and FP32 driven by the same steps
+    # time to record them, and FP32 driven by the same steps.  Beside it, the
+    # floor of any FP32 state on this flow: an FP64 run whose density alone is
+    # rounded to FP32 after every step (all arithmetic FP64), compared with
+    # the plain FP64 run.
+    n = prob.cells
     g64 = Grid.from_problem(prob, prec="fp64")
-    taus = []
-    for _ in range(steps):
-        g64.step(1)
-        taus.append(g64.time()[1])
-    rho64 = g64.get("rho")
-    del g64
     g32 = Grid.from_problem(prob, prec="fp32")
-    for tau in taus:
+    gr = Grid.from_problem(prob, prec="fp64")
+
+    def rho_of(g):
+        return g.state.view(torch.float64 if g.desc.prec == 1 else torch.float32)[:n].double()
+
+    def l1(a, b):
+        return float((a - b).abs().sum() / a.abs().sum())
+
+    marks = {}
+    for s in range(1, steps + 1):
+        g64.step(1)
+        tau = g64.time()[1]
         g32.step(1, dt_fixed=float(tau))
-    rho32 = g32.get("rho")
-    del g32
+        gr.step(1, dt_fixed=float(tau))
+        gr.sync()
+        v = gr.state.view(torch.float64)
+        v[:n] = v[:n].float().double()
+        if s in (100, steps):
+            g32.sync()
+            marks[s] = (l1(rho_of(g64), rho_of(g32)), l1(rho_of(g64), rho_of(gr)))
+    del g64, g32, gr
     torch.cuda.empty_cache()
-    out["l1_rho_fp32_vs_fp64_same_steps"] = float(np.sum(np.abs(rho32 - rho64)) / np.sum(np.abs(rho64)))
+    out["l1_rho_fp32_vs_fp64_same_steps"] = marks[steps][0]
+    out["l1_rho_fp64_with_rho_rounded_to_fp32_each_step"] = marks[steps][1]
+    if 100 in marks and steps != 100:
+        out["l1_rho_fp32_vs_fp64_after_100_steps"] = marks[100][0]
+        out["l1_rho_fp64_with_rho_rounded_after_100_steps"] = marks[100][1]
     return out
 
 
@@ -301,7 +334,8 @@ def run_suite():
     stop time with CFL steps (host-driven chunks of 64 steps): two blast
     waves (1-D, 2400 cells, FP64, t = 0.038), Sedov (100^3, t = 0.05) and
     Kelvin-Helmholtz (256^2, t = 1) in FP32 and FP64; tile shapes from the
-    autotuner."""
+    autotuner; and Rayleigh-Taylor (100 x 600, t = 6) with the growth rate
+    of its seeded mode."""
     import torch
 
     from paper_1607_01105_amd import autotune
@@ -311,7 +345,8 @@ def run_suite():
     out = {}
     for name, prob, precs in (("blast_waves_2400", W.blast_waves(), ("fp64",)),
                               ("sedov_100", W.sedov(100), ("fp32", "fp64")),
-                              ("kelvin_helmholtz_256", W.kelvin_helmholtz(256), ("fp32", "fp64"))):
+                              ("kelvin_helmholtz_256", W.kelvin_helmholtz(256), ("fp32", "fp64")),
+                              ("rayleigh_taylor_100x600", W.rayleigh_taylor(t_stop=6.0), ("fp32", "fp64"))):
         out[name] = {}
         for prec in precs:
             tile = autotune.tune_grid(prob, prec, steps=8, warmup=2)["tile"]
@@ -322,6 +357,24 @@ def run_suite():
             sec = time.perf_counter() - t0
             out[name][prec] = {"steps": n, "t": t, "zone_updates_per_s": prob.cells * n / sec, "seconds": sec,
                                "tile": list(ppml_tile_shape(prob.ndim, tile))}
+            if name.startswith("rayleigh_taylor"):
+                # growth of the seeded mode at the unstable interface over
+                # t = 3 .. 6 (untimed rerun), against linear theory sqrt(A g k)
+                import numpy as np
+
+                k = 4.0 * math.pi
+                x, y = prob.centres(0), prob.centres(1)
+                sel = np.abs(y + 0.75) <= 0.25
+                g2 = Grid.from_problem(prob, prec=prec, tile=tile)
+                ts = np.arange(3.0, 6.01, 0.5)
+                amp = []
+                for tt in ts:
+                    g2.run_to(float(tt))
+                    vy = (g2.get("my") / g2.get("rho"))[0]
+                    amp.append(2.0 * float(abs(np.mean(vy[sel] * np.cos(k * x)[None, :]))))
+                out[name][prec]["growth_rate"] = float(np.polyfit(ts, np.log(amp), 1)[0])
+                out[name][prec]["growth_rate_linear_theory"] = math.sqrt((1.0 / 3.0) * 0.1 * k)
+                del g2
             del g
         torch.cuda.empty_cache()
     return out
@@ -446,31 +499,26 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(prob, min_seconds=10.0, max_steps=30):
-    """The FP64 oracle, untuned, on this host's cores: steps of the full 256^3
-    workload until at least min_seconds of CPU work (bounded sample)."""
+def cpu_baseline(prob, steps=100):
+    """The FP64 oracle, untuned, on this host's cores: the full workload
+    (steps of the 256^3 box), timed around the step loop, then one step on a
+    single core.  Returns the baseline and the oracle's time steps and final
+    fields, against which the GPU runs are checked after the run."""
     import oracle
 
     o = oracle.Oracle(prob.ndim, prob.n, prob.lo, prob.hi, prob.gamma, prob.cfl, bc=prob.bc)
     o.set_primitive(prob.rho, prob.vx, prob.vy, prob.vz, prob.p)
-    steps = 0
-    sec = 0.0
-    while steps < max_steps and sec < min_seconds:
-        tau = o.dt()
-        t0 = time.perf_counter()
-        o.step(tau)
-        sec += time.perf_counter() - t0
-        steps += 1
     cores = oracle.max_threads()
-    # the same stepping on one core (results are independent of the threads)
+    t0 = time.perf_counter()
+    taus = [float(t) for t in o.run(steps)]
+    sec = time.perf_counter() - t0
+    final = [o.get(f) for f in range(6)]
+    # one more step on one core (results are independent of the threads)
     oracle.set_threads(1)
-    steps1, sec1 = 0, 0.0
-    while steps1 < 1 or (sec1 < 5.0 and steps1 < max_steps):
-        tau = o.dt()
-        t0 = time.perf_counter()
-        o.step(tau)
-        sec1 += time.perf_counter() - t0
-        steps1 += 1
+    tau = o.dt()
+    t0 = time.perf_counter()
+    o.step(tau)
+    sec1 = time.perf_counter() - t0
     oracle.set_threads(cores)
     del o
     model = None
@@ -481,11 +529,40 @@ def cpu_baseline(prob, min_seconds=10.0, max_steps=30):
                 break
     except OSError:
         pass
-    return {"value": prob.cells * steps / sec, "unit": "zone-updates/s", "cores": cores, "kind": "oracle",
+    base = {"value": prob.cells * steps / sec, "unit": "zone-updates/s", "cores": cores, "kind": "oracle",
             "cpu_model": model, "nproc": os.cpu_count(),
-            "sample": f"first {steps} steps of the same 256^3 workload ({prob.cells * steps} zone-updates), "
-                      f"FP64, {sec:.1f} s of stepping on {cores} threads; then {steps1} more step(s) on 1 thread",
-            "one_core_value": prob.cells * steps1 / sec1}
+            "sample": f"the full workload: {steps} steps of the 256^3 box ({prob.cells * steps} zone-updates), "
+                      f"FP64, {sec:.1f} s of stepping on {cores} threads; then 1 step on 1 thread",
+            "one_core_value": prob.cells / sec1}
+    return base, taus, final
+
+
+def parity_after_run(prob, taus, final):
+    """GPU FP64 and FP32 runs of the whole workload driven by the oracle's
+    time steps, compared with the oracle's final state: per field the
+    normwise relative error max|a - b| / max|b| (FP64) and the L1 relative
+    error of the density (FP32)."""
+    import numpy as np
+    import torch
+
+    from paper_1607_01105_amd.ppml import Grid
+
+    out = {"steps": len(taus), "against": "FP64 oracle, same time steps"}
+    for prec in ("fp64", "fp32"):
+        g = Grid.from_problem(prob, prec=prec)
+        for tau in taus:
+            g.step(1, dt_fixed=tau)
+        g.sync()
+        if prec == "fp64":
+            out["fp64_normwise_rel_err_per_field"] = {
+                name: float(np.max(np.abs(g.get(f) - final[f])) / max(np.max(np.abs(final[f])), 1e-300))
+                for f, name in enumerate(("rho", "mx", "my", "mz", "Et", "e"))}
+        else:
+            r = g.get("rho")
+            out["fp32_l1_rho"] = float(np.sum(np.abs(r - final[0])) / np.sum(np.abs(final[0])))
+        del g
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -497,7 +574,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched and served runs")
-    ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--serve-requests", type=int, default=400, help="requests per served load")
     ap.add_argument("--no-tune", action="store_true", help="use the default tile shape instead of the autotuner's")
     ap.add_argument("--leg", choices=["gravity", "galaxy", "disk", "disk_isothermal", "suite", "batched", "riemann_1d"],
                     default=None,
@@ -599,32 +676,40 @@ def main():
                                                   for v, t in res[p]["tuned"]["ms_per_step"].items()}}
                      for p in res if res[p]["tuned"]},
         "kernels_ms": {"euler": r["ms_euler"], "lagr": r["ms_lagr"]},
+        # the dominant kernel against the published vector peak of its type
+        # (FP32 157.3 TFLOP/s counts packed FP32 instructions, which this build
+        # does not use; the rate of the unpacked FMA it does use, 78.6, is
+        # beside it), with the VALU issue fraction that shows the bound and the
+        # whole step's compulsory HBM bytes against 8 TB/s
         "roofline": {"bound": "alu", "kernel": "k_" + kern, "achieved": achieved_tflops,
-                     "peak": VALU_PEAK_TFLOPS[dt], "unit": "TFLOP/s", "frac": achieved_tflops / VALU_PEAK_TFLOPS[dt],
+                     "peak": FP32_VECTOR_PEAK_TFLOPS if dt == "f32" else FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tflops / (FP32_VECTOR_PEAK_TFLOPS if dt == "f32" else FP64_VECTOR_PEAK_TFLOPS),
                      "traffic": traffic, "algorithmic_flop_per_zone": ALGO_FLOP_PER_ZONE_3D[kern],
+                     "unpacked_fma_peak": VALU_PEAK_TFLOPS[dt],
+                     "frac_of_unpacked_fma_peak": achieved_tflops / VALU_PEAK_TFLOPS[dt],
                      "valu_issue": valu_issue,
-                     "launch_ms": ms_k, "published_peak": FP32_VECTOR_PEAK_TFLOPS if dt == "f32" else FP64_VECTOR_PEAK_TFLOPS,
+                     "launch_ms": ms_k,
                      "hbm": {"achieved_GBs": achieved_gbs, "peak_GBs": HBM_PEAK_GBS,
                              "frac": achieved_gbs / HBM_PEAK_GBS,
                              "algorithmic_bytes_per_zone": algorithmic_bytes_per_zone(kern, 3, width),
-                             "measured_GBs": (traffic / (ms_k * 1e-3) / 1e9) if traffic else None}},
+                             "measured_GBs": (traffic / (ms_k * 1e-3) / 1e9) if traffic else None},
+                     "step_hbm": {"compulsory_bytes_per_zone": 2 * 6 * width,
+                                  "achieved_GBs": 2 * 6 * width * cells / (r["ms"] / args.steps * 1e-3) / 1e9,
+                                  "peak_GBs": HBM_PEAK_GBS,
+                                  "frac": 2 * 6 * width * cells / (r["ms"] / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                  "target_frac": 0.6}},
     }
     if "fp64" in res and "fp32" in res:
-        import numpy as np
-
         r64 = res["fp64"]
         out["fp64"] = {"value": cells * args.steps / (r64["ms"] * 1e-3), "ms_per_step": r64["ms"] / args.steps,
                        "kernels_ms": {"euler": r64["ms_euler"], "lagr": r64["ms_lagr"]},
                        "tile": list(ppml_tile_shape(3, r64["tuned"]["tile"] if r64["tuned"] else 0))}
-        out["l1_rho_fp32_vs_fp64"] = float(np.sum(np.abs(res["fp32"]["rho"] - r64["rho"])) / np.sum(np.abs(r64["rho"])))
     if not args.no_batch and "fp32" in res:
         print("[bench] batched configuration", file=sys.stderr, flush=True)
         out["batched"] = run_batched()
         print(f"[bench] batched: {out['batched']['speedup']:.1f}x over plain launches", file=sys.stderr, flush=True)
         print("[bench] served configuration", file=sys.stderr, flush=True)
-        out["served"] = run_served(n_requests=args.serve_requests, capacity_zu_per_s=value)
-        print(f"[bench] served: p50 {out['served']['latency_p50_s']:.3f} s, p99 {out['served']['latency_p99_s']:.3f} s",
-              file=sys.stderr, flush=True)
+        out["served"] = run_served(n_requests=args.serve_requests)
     if not args.no_batch:
         print("[bench] disk configuration", file=sys.stderr, flush=True)
         out["disk"] = run_disk()
@@ -639,11 +724,16 @@ def main():
         out["suite"] = run_suite()
         print("[bench] self-gravity workload", file=sys.stderr, flush=True)
         out["gravity"] = run_gravity()
-        print("[bench] galactic-disk configuration", file=sys.stderr, flush=True)
-        out["galaxy"] = run_galaxy()
     if not args.no_cpu:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(prob)
+        print("[bench] cpu baseline: the oracle runs the full workload", file=sys.stderr, flush=True)
+        out["cpu_baseline"], taus, final = cpu_baseline(prob, steps=WORKLOAD_STEPS)
+        print(f"[bench] oracle: {out['cpu_baseline']['value']:.3e} zone-updates/s on "
+              f"{out['cpu_baseline']['cores']} threads", file=sys.stderr, flush=True)
+        out["parity_after_run"] = parity_after_run(prob, taus, final)
+        pr = out["parity_after_run"]
+        print(f"[bench] after {pr['steps']} steps vs oracle: fp64 max normwise "
+              f"{max(pr['fp64_normwise_rel_err_per_field'].values()):.2e}, fp32 L1(rho) {pr['fp32_l1_rho']:.2e}",
+              file=sys.stderr, flush=True)
     print(json.dumps(out))
 
 

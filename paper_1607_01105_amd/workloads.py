@@ -203,6 +203,35 @@ def kelvin_helmholtz(n: int = 256, gamma: float = 1.4, cfl: float = 0.4, t_stop:
                    zero.copy(), zero.copy(), p, None, None, t_stop)
 
 
+def rayleigh_taylor(n: tuple = (100, 600), g: float = 0.1, gamma: float = 1.4, cfl: float = 0.2,
+                    p_top: float = 0.15, amp: float = 1e-2, band: float = 0.01, waves: int = 1,
+                    t_stop: float | None = None) -> Problem:
+    """Rayleigh-Taylor instability (the paper's test, under a repaired
+    reading): [-0.25, 0.25] x [-1.5, 1.5], rho = 2 for |y| <= 0.75 and 1
+    outside, gamma = 1.4, uniform gravity g = 0.1 along -y (the potential
+    g y), and the pressure of hydrostatic equilibrium
+    p(y) = p_top + g * (mass per unit area above y), continuous and positive
+    (p_top = 0.15 at the top wall).  The heavy slab then lies over light gas
+    at y = -0.75 (unstable) and under it at y = +0.75 (stable).  The printed
+    perturbation, restricted to a band of half-width 0.01 around both
+    interfaces, with one mode that is periodic in x:
+    v_y = amp (1 + cos(2 pi y)) cos(2 pi waves x / 0.5).  Periodic in x,
+    reflecting walls at y = -1.5 and 1.5; 100 x 600 cells as printed."""
+    n3, lo, hi = _grid(2, tuple(n), (-0.25, -1.5), (0.25, 1.5))
+    X, Y, Z = _mesh(n3, lo, hi)
+    rho = np.where(np.abs(Y) <= 0.75, 2.0, 1.0)
+    # mass per unit area between y and the top wall
+    above = np.where(Y >= 0.75, 1.0 * (1.5 - Y),
+                     np.where(Y >= -0.75, 0.75 + 2.0 * (0.75 - Y), 0.75 + 3.0 + 1.0 * (-0.75 - Y)))
+    p = p_top + g * above
+    vy = np.where(np.abs(np.abs(Y) - 0.75) <= band,
+                  amp * (1.0 + np.cos(2.0 * math.pi * Y)) * np.cos(2.0 * math.pi * waves * X / 0.5), 0.0)
+    zero = np.zeros_like(rho)
+    bc = [("periodic", "periodic"), ("reflect", "reflect"), ("periodic", "periodic")]
+    return Problem(f"rayleigh_taylor_{n3[0]}x{n3[1]}", 2, n3, lo, hi, gamma, cfl, bc, rho, zero.copy(), vy,
+                   zero.copy(), p, ("uniform", 0.0, g, 0.0), None, t_stop)
+
+
 def _mode_set(kmax: float, ndim: int):
     r = int(math.floor(kmax))
     ks = []
