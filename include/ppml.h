@@ -240,8 +240,10 @@ int ppml_get_timing_split(ppml_grid *g, double ms[3], int64_t *nsteps);
 
 /* ---- Batches: many independent grids stepped together ------------------
  * A batch steps all its grids in the same kernel launches (one Eulerian and
- * one Lagrangian launch per step and dimensionality present), optionally
- * recorded once into a HIP graph and replayed.  Each grid keeps its own
+ * one Lagrangian launch per step and dimensionality present; the launch
+ * chains of different dimensionalities run concurrently on streams the
+ * batch forks from its stream and joins back), optionally recorded once into
+ * a HIP graph and replayed.  Each grid keeps its own
  * time step (Sec. 2.1 CFL condition of its own state), time, maxima and
  * error word, so a grid's results are the same alone and in any batch.
  * Grids keep their caller-owned memory; the batch owns two small tables

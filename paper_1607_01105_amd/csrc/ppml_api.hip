@@ -1226,6 +1226,12 @@ struct ppml_batch {
     hipGraphExec_t exec;
     int graph_nsteps;
     long long graph_version;
+    // grids of different dimensionalities share nothing: their launch chains
+    // run as parallel branches (streams forked from and joined to the batch
+    // stream, default priority), so the small 1-D launches overlap the 2-D
+    // and 3-D ones instead of adding their dispatch time
+    hipStream_t side[4];
+    hipEvent_t ev_fork, ev_join[4];
 };
 
 namespace {
@@ -1266,29 +1272,50 @@ int batch_rebuild(ppml_batch *b)
     return PPML_OK;
 }
 
-template <typename T, int NDIM> void batch_stage(ppml_batch *b, bool lagr)
+template <typename T, int NDIM> void batch_stage(ppml_batch *b, bool lagr, hipStream_t st)
 {
     if (!b->gn[NDIM]) return;
     with_tile<NDIM>(b->tile[NDIM], [&](auto tl) {
         using TL = decltype(tl);
         const BatchEntry *e = b->d_ents + b->goff[NDIM];
         if (lagr)
-            k_lagr_batch<T, NDIM, TL::tx, TL::ty, LG<T>::g><<<b->gtiles[NDIM], TL::nt, 0, b->stream>>>(e, b->gn[NDIM]);
+            k_lagr_batch<T, NDIM, TL::tx, TL::ty, LG<T>::g><<<b->gtiles[NDIM], TL::nt, 0, st>>>(e, b->gn[NDIM]);
         else
-            k_euler_batch<T, NDIM, TL::tx, TL::ty><<<b->gtiles[NDIM], TL::nt, 0, b->stream>>>(e, b->gn[NDIM]);
+            k_euler_batch<T, NDIM, TL::tx, TL::ty><<<b->gtiles[NDIM], TL::nt, 0, st>>>(e, b->gn[NDIM]);
     });
 }
 
-template <typename T> void batch_enqueue(ppml_batch *b, int nsteps)
+template <typename T, int NDIM> void batch_chain(ppml_batch *b, int nsteps, hipStream_t st)
 {
     for (int s = 0; s < nsteps; s++) {
-        batch_stage<T, 1>(b, false);
-        batch_stage<T, 2>(b, false);
-        batch_stage<T, 3>(b, false);
-        batch_stage<T, 1>(b, true);
-        batch_stage<T, 2>(b, true);
-        batch_stage<T, 3>(b, true);
+        batch_stage<T, NDIM>(b, false, st);
+        batch_stage<T, NDIM>(b, true, st);
     }
+}
+
+// nsteps steps of every grid: one chain of stage launches per dimensionality
+// present; with more than one, each chain runs on a side stream forked from
+// the batch stream and joined back to it.
+template <typename T> int batch_enqueue(ppml_batch *b, int nsteps)
+{
+    int present = 0;
+    for (int nd = 1; nd <= 3; nd++) present += b->gn[nd] ? 1 : 0;
+    const bool fork = present > 1;
+    if (fork) HIPCHK(hipEventRecord(b->ev_fork, b->stream));
+    for (int nd = 1; nd <= 3; nd++) {
+        if (!b->gn[nd]) continue;
+        hipStream_t st = fork ? b->side[nd] : b->stream;
+        if (fork) HIPCHK(hipStreamWaitEvent(st, b->ev_fork, 0));
+        if (nd == 1) batch_chain<T, 1>(b, nsteps, st);
+        else if (nd == 2) batch_chain<T, 2>(b, nsteps, st);
+        else batch_chain<T, 3>(b, nsteps, st);
+        HIPCHK(hipGetLastError());
+        if (fork) {
+            HIPCHK(hipEventRecord(b->ev_join[nd], st));
+            HIPCHK(hipStreamWaitEvent(b->stream, b->ev_join[nd], 0));
+        }
+    }
+    return PPML_OK;
 }
 
 void batch_drop_graph(ppml_batch *b)
@@ -1328,8 +1355,18 @@ int ppml_batch_create(int32_t capacity, size_t budget_bytes, void *hip_stream, p
     b->exec = nullptr;
     b->graph_nsteps = -1;
     b->graph_version = -1;
+    for (int nd = 0; nd < 4; nd++) {
+        b->side[nd] = nullptr;
+        b->ev_join[nd] = nullptr;
+    }
+    b->ev_fork = nullptr;
     hipError_t e = hipMalloc(&b->d_ents, (size_t)capacity * sizeof(BatchEntry));
     if (e == hipSuccess) e = hipMalloc(&b->d_steps, (size_t)capacity * sizeof(int));
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+    for (int nd = 1; nd <= 3 && e == hipSuccess; nd++) {
+        e = hipStreamCreateWithFlags(&b->side[nd], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join[nd], hipEventDisableTiming);
+    }
     if (e == hipSuccess) e = hipHostMalloc(&b->h_ents, (size_t)capacity * sizeof(BatchEntry), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc(&b->h_steps, (size_t)capacity * sizeof(int), hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -1337,6 +1374,11 @@ int ppml_batch_create(int32_t capacity, size_t budget_bytes, void *hip_stream, p
         if (b->d_steps) (void)hipFree(b->d_steps);
         if (b->h_ents) (void)hipHostFree(b->h_ents);
         if (b->h_steps) (void)hipHostFree(b->h_steps);
+        for (int nd = 1; nd <= 3; nd++) {
+            if (b->side[nd]) (void)hipStreamDestroy(b->side[nd]);
+            if (b->ev_join[nd]) (void)hipEventDestroy(b->ev_join[nd]);
+        }
+        if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
         delete b;
         return fail(PPML_ENOMEM, "batch tables: %s", hipGetErrorString(e));
     }
@@ -1419,10 +1461,14 @@ int ppml_batch_step(ppml_batch *b, int32_t nsteps, const int32_t *steps_per_slot
         if (!b->exec || b->graph_version != b->version || b->graph_nsteps != nsteps) {
             batch_drop_graph(b);
             HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-            if (fp64) batch_enqueue<double>(b, nsteps);
-            else batch_enqueue<float>(b, nsteps);
+            const int erc = fp64 ? batch_enqueue<double>(b, nsteps) : batch_enqueue<float>(b, nsteps);
             hipGraph_t gr = nullptr;
-            HIPCHK(hipStreamEndCapture(b->stream, &gr));
+            const hipError_t ce = hipStreamEndCapture(b->stream, &gr);
+            if (erc) {
+                if (gr) (void)hipGraphDestroy(gr);
+                return erc;
+            }
+            HIPCHK(ce);
             b->graph = gr;
             HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
             b->graph_nsteps = nsteps;
@@ -1430,9 +1476,8 @@ int ppml_batch_step(ppml_batch *b, int32_t nsteps, const int32_t *steps_per_slot
         }
         HIPCHK(hipGraphLaunch(b->exec, b->stream));
     } else {
-        if (fp64) batch_enqueue<double>(b, nsteps);
-        else batch_enqueue<float>(b, nsteps);
-        HIPCHK(hipGetLastError());
+        const int erc = fp64 ? batch_enqueue<double>(b, nsteps) : batch_enqueue<float>(b, nsteps);
+        if (erc) return erc;
     }
     return PPML_OK;
 }
@@ -1484,6 +1529,11 @@ int ppml_batch_destroy(ppml_batch *b)
     (void)hipFree(b->d_steps);
     (void)hipHostFree(b->h_ents);
     (void)hipHostFree(b->h_steps);
+    for (int nd = 1; nd <= 3; nd++) {
+        (void)hipStreamDestroy(b->side[nd]);
+        (void)hipEventDestroy(b->ev_join[nd]);
+    }
+    (void)hipEventDestroy(b->ev_fork);
     delete b;
     return PPML_OK;
 }
