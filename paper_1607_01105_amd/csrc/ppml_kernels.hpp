@@ -23,6 +23,36 @@ namespace ppml {
 
 template <typename T> __device__ __forceinline__ T ldg(const T *p) { return __builtin_nontemporal_load(p); }
 
+// Job spaces of two kinds (NA x jobs, then NB y jobs) spread over the waves
+// of a work group of NT threads: whole wave-rounds of 64 jobs hold one kind
+// (wave-rounds 0 .. QA-1 the x jobs, QA .. QA+QB-1 the y jobs), and round r
+// of wave w takes wave-round r NW + w.  No wave runs both kinds in one round
+// and the partly filled rounds fall on different waves, so the waves of a
+// group finish a job phase close together.  job() gives the job of a lane
+// (x: 0 .. NA-1, y: NA .. NA+NB-1) or NA + NB for none.
+template <int NT, int NA, int NB> struct JobMap {
+    static_assert(NT % 64 == 0, "work groups of whole waves");
+    static constexpr int NW = NT / 64;
+    static constexpr int QA = (NA + 63) / 64;
+    static constexpr int QB = (NB + 63) / 64;
+    static constexpr int R = (QA + QB + NW - 1) / NW;  // rounds per wave
+    static __device__ __forceinline__ int job(int r, int wave, int lane)
+    {
+        const int q = r * NW + wave;
+        if (q < QA) {
+            const int j = q * 64 + lane;
+            return j < NA ? j : NA + NB;
+        }
+        const int j = NA + (q - QA) * 64 + lane;
+        return j < NA + NB ? j : NA + NB;
+    }
+    // first wave-round of the y jobs that this wave takes
+    static __device__ __forceinline__ int first_b(int wave) { return QA + ((wave - QA % NW) % NW + NW) % NW; }
+};
+
+// The wave's index in its work group, as a wave-uniform (scalar) value.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6); }
+
 // s_waitcnt operand that waits for every outstanding vector-memory operation
 // of the wave (vmcnt = 0) and leaves the export and LDS/scalar counters
 // unconstrained (gfx9 encoding: vmcnt[3:0], expcnt[6:4], lgkmcnt[11:8],
@@ -271,6 +301,7 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
+    const int wv = wave_id(), ln = tid & 63;  // the wave (scalar) and the lane
     const int x0 = bx * TX, y0 = by * TY;
     const int nx = gp.n[0], ny = gp.n[1], nz = gp.n[2];
     const long long N = gp.ncell;
@@ -499,7 +530,10 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
         // parabolas of v_d and p, two neighbouring cells per job (shared slopes
         // and interface value): x pairs of each row, then y pairs of each
         // column, in one job space
-        for (int j = tid; j < NXR + NYR; j += NT) {
+        using JP = JobMap<NT, NXR, NYR>;
+#pragma unroll 1
+        for (int rq = 0; rq < JP::R; rq++) {
+            const int j = JP::job(rq, wv, ln);
             if (j < NXR) {
                 const int pr = j % PXR, cy = j / PXR;
                 const int cx = 2 * pr;  // first cell of the pair (tile-rel x = cx - 1)
@@ -509,7 +543,7 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
                               s_vx[li + 3], xv[o], xv[o + 1]);
                 parabola_pair(gp.first_order, s_p[li - 2], s_p[li - 1], s_p[li], s_p[li + 1], s_p[li + 2],
                               s_p[li + 3], xp[o], xp[o + 1]);
-            } else if constexpr (NDIM >= 2) {
+            } else if (NDIM >= 2 && j < NXR + NYR) {
                 const int jj = j - NXR;
                 const int cx = jj % TX, pr = jj / TX;
                 const int cy = 2 * pr;  // first cell of the pair (tile-rel y = cy - 1)
@@ -522,7 +556,13 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
             }
         }
         __syncthreads();
-        for (int j = tid; j < NXI; j += NT) {
+        // Riemann problems: x interfaces, then y interfaces, each spread over
+        // the waves so that the wave with a partial x round is not the one
+        // with the partial y round
+        using JR = JobMap<NT, NXI, NDIM >= 2 ? NYI : 0>;
+        for (int qw = wv; qw < JR::QA; qw += JR::NW) {
+            const int j = qw * 64 + ln;
+            if (j >= NXI) continue;
             const int ix = j % (TX + 1), cy = j / (TX + 1);
             const int la = (cy + HY) * PW + ix - 1 + HX, lb = la + 1;
             const int pa = cy * (TX + 2) + ix, pb = pa + 1;
@@ -530,7 +570,9 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
                             gam, tau, hx, tohx);
         }
         if constexpr (NDIM >= 2) {
-            for (int j = tid; j < NYI; j += NT) {
+            for (int qw = JR::first_b(wv); qw < JR::QA + JR::QB; qw += JR::NW) {
+                const int j = (qw - JR::QA) * 64 + ln;
+                if (j >= NYI) continue;
                 const int cx = j % TX, iy = j / TX;
                 const int la = (iy - 1 + HY) * PW + cx + HX, lb = la + PW;
                 const int pa = iy * TX + cx, pb = pa + TX;
@@ -673,6 +715,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
         ctrl->slot_cur = sl ^ 1;
     }
     const int tx = tid % TX, ty = tid / TX;
+    const int wv = wave_id(), ln = tid & 63;  // the wave (scalar) and the lane
     const int x0 = bx * TX, y0 = by * TY;
     const int nx = gp.n[0], ny = gp.n[1], nz = gp.n[2];
     const long long N = gp.ncell;
@@ -950,7 +993,21 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
         T (*sf)[PS] = s_f[PIPE ? (k & 1) : 0];  // cross tile of plane k
         T acc[NF];
         T own[NF];  // U^{n+1/2} of the thread's own cell, read from the tiles
-        constexpr int NJF = (NXI + NYI + NT - 1) / NT;
+        // flux jobs: round 0 the x interfaces 0 .. NT-1, round 1 the y
+        // interfaces 0 .. NT-1, the last round the remaining x interfaces
+        // (wave 0) and y interfaces (wave 1): no wave takes both kinds in one
+        // round or more than three jobs, and the kind of the first two rounds
+        // is known at compile time
+        static_assert(NXI >= NT && NXI - NT <= 64 && (NDIM < 2 || (NYI >= NT && NYI - NT <= 64 && NT >= 128)),
+                      "flux job rounds");
+        constexpr int NJF = NDIM >= 2 ? 3 : 2;
+        auto flux_job = [&](int r) -> int {
+            if (r == 0) return tid;
+            if (NDIM >= 2 && r == 1) return NXI + tid;
+            if (wv == 0) return NT + ln < NXI ? NT + ln : NXI + NYI;
+            if (NDIM >= 2 && wv == 1) return NXI + NT + ln;
+            return NXI + NYI;
+        };
         T vhr[NJF];  // interface velocities of this thread's flux jobs
         // velocity ring slots of planes k-1, k, k+1
         const int sm = NDIM == 3 ? ((k - 1) % 3 + 3) % 3 : 0;
@@ -1083,7 +1140,10 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                     }
                 }
             } else {
-                for (int j = tid; j < NXQ + NYQ; j += NT) {
+                using JQ = JobMap<NT, NXQ, NYQ>;
+#pragma unroll 1
+                for (int rq = 0; rq < JQ::R; rq++) {
+                    const int j = JQ::job(rq, wv, ln);
                     if (j < NXQ) {
                         const int fxi = j % (TX + 3), cy = j / (TX + 3);
                         const int l = (cy + HY) * PW + fxi;  // q of tile-rel cells fxi-3 .. fxi
@@ -1095,7 +1155,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                             const T db = limited_slope(q[l + 1], q[l + 2], q[l + 3]);
                             s_qx[g][j] = interface_value(q[l + 1], q[l + 2], da, db);
                         }
-                    } else if constexpr (NDIM >= 2) {
+                    } else if (NDIM >= 2 && j < NXQ + NYQ) {
                         const int jj = j - NXQ;
                         const int cx = jj % TX, fyi = jj / TX;
                         const int l = fyi * PW + cx + HX;  // rows fyi-3 .. fyi (tile-rel)
@@ -1117,7 +1177,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
             T Fr[NJF][G];
 #pragma unroll
             for (int r = 0; r < NJF; r++) {
-                const int j = tid + r * NT;
+                const int j = flux_job(r);
                 if (j < NXI) {
                     const int ix = j % (TX + 1), cy = j / (TX + 1);
                     if (pass == 0) {
@@ -1202,7 +1262,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < NJF; r++) {
-                const int j = tid + r * NT;
+                const int j = flux_job(r);
                 if (j < NXI) {
 #pragma unroll
                     for (int g = 0; g < G; g++)
