@@ -370,6 +370,39 @@ template <typename T> __device__ __forceinline__ T upwind_flux(T vh, T z, const 
     return vh * fs;
 }
 
+// Product build: of a cell's monotonised parabola the Lagrangian stage needs
+// only the two edge values and the cell value (the curvature coefficient is
+// 6 c - 3 (L + R)), and of the mean over the strip of width z h next to an
+// interface only the weights of the upwind cell's near edge, far edge and
+// value.  Expanding either strip mean above with that coefficient gives
+//   (1 - z)^2 near + z (z - 1) far + z (3 - 2 z) c,
+// weights that depend on z alone and serve every field of the interface.
+template <typename T> struct Edges {
+    T L, R, C;
+};
+template <typename T> __device__ __forceinline__ Edges<T> mono_edges(int first_order, T c, T l, T r)
+{
+    if (first_order) return Edges<T>{c, c, c};
+    // the rules of monotonize, in terms of the one-sided jumps
+    const T dl = c - l, dr = r - c;
+    const bool flat = dl * dr <= T(0);
+    const T L = flat ? c : (dabs(dl) > K<T>::two * dabs(dr) ? c - K<T>::two * dr : l);
+    const T R = flat ? c : (dabs(dr) > K<T>::two * dabs(dl) ? c + K<T>::two * dl : r);
+    return Edges<T>{L, R, c};
+}
+template <typename T> struct StripW {
+    T near, far, mid;
+};
+template <typename T> __device__ __forceinline__ StripW<T> strip_weights(T z)
+{
+    const T y = T(1) - z;
+    return StripW<T>{y * y, -(z * y), z * (K<T>::three - K<T>::two * z)};
+}
+template <typename T> __device__ __forceinline__ T strip_mean(const StripW<T> &w, T near, T far, T c)
+{
+    return w.near * near + (w.far * far + w.mid * c);
+}
+
 // Density-weighted interface velocity (Sec. 2.3).
 template <typename T> __device__ __forceinline__ T interface_velocity(T va, T sa, T vb, T sb)
 {

@@ -50,6 +50,14 @@ template <int NT, int NA, int NB> struct JobMap {
     static __device__ __forceinline__ int first_b(int wave) { return QA + ((wave - QA % NW) % NW + NW) % NW; }
 };
 
+// The value of the previous lane of the 16-lane DPP row (row_shr:1); lane
+// 0 of each row gets its own value.  Every lane of the row must be active.
+__device__ __forceinline__ float dpp_prev16(float v)
+{
+    const int i = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, 0x111, 0xF, 0xF, false));
+}
+
 // The wave's index in its work group, as a wave-uniform (scalar) value.
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6); }
 
@@ -726,7 +734,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
     const T hx = (T)gp.h[0], hy = (T)gp.h[1], hz = (T)gp.h[2];
     const T ihx = (T)gp.inv_h[0], ihy = (T)gp.inv_h[1], ihz = (T)gp.inv_h[2];
     const T tohx = (T)(tau_d * gp.inv_h[0]), tohy = (T)(tau_d * gp.inv_h[1]), tohz = (T)(tau_d * gp.inv_h[2]);
-    (void)hy; (void)ihy; (void)tohy; (void)hz; (void)ihz; (void)tohz; (void)tohx; (void)hx;
+    (void)hy; (void)ihy; (void)tohy; (void)hz; (void)ihz; (void)tohz; (void)tohx; (void)hx; (void)ihx; (void)tau;
     const double thr = gp.vacuum_ratio * ctrl->rho_mean0;
 
     const int gx = x0 + tx, gy = y0 + ty;
@@ -789,16 +797,25 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
         }
     }
 
-    // z pipeline registers (3-D), one set per field
+    // z pipeline registers (3-D), one set per field.  The profile of the
+    // previous cell: its parabola in the exact build, its edge values and
+    // value in the product build.
+#ifdef PPML_EXACT
+    using Prof = Parab<T>;
+    const Prof prof_one{T(1), T(1), T(0)};
+#else
+    using Prof = Edges<T>;
+    const Prof prof_one{T(1), T(1), T(1)};
+#endif
     T q0[NF], q1[NF], q2[NF], dmq[NF], qI[NF], Fzp[NF];
-    Parab<T> pprev[NF];
+    Prof pprev[NF];
 #pragma unroll
     for (int f = 0; f < NF; f++) {
         q0[f] = q1[f] = q2[f] = T(1);
         dmq[f] = T(0);
         qI[f] = T(1);
         Fzp[f] = T(0);
-        pprev[f] = Parab<T>{T(1), T(1), T(0)};
+        pprev[f] = prof_one;
     }
     T sz0 = 1, sz1 = 1, sz2 = 1, sz3 = 1;  // sqrt(rho) of the column at m-3..m
     T vtz_prev = 0;                        // transverse velocity of the column at m-3
@@ -824,6 +841,41 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
         }
     };
     if constexpr (PIPE) dma_cross(z0);
+    // the cross tile of plane kk arrived by transfer: once this wave's
+    // transfers have landed, each thread mirrors the normal momenta at
+    // reflecting faces and writes the state of inflow faces into the slots
+    // it owns (every slot it owns was moved by its own wave)
+    auto fix_cross = [&](int kk) {
+        T (*sf)[PS] = s_f[kk & 1];
+        __builtin_amdgcn_s_waitcnt(VMCNT0);
+        if (flips & 0xFFFFu) {
+#pragma unroll
+            for (int r = 0; r < RC; r++) {
+                if (ccode[r] < 0) continue;
+                const int li = tid + r * NT;
+                const unsigned fl = flips >> (2 * r);
+                if (fl & 1) sf[1][li] = -sf[1][li];
+                if (NDIM >= 2 && (fl & 2)) sf[2][li] = -sf[2][li];
+            }
+        }
+        if (gp.any_inflow) {
+            // ghosts of inflow faces take the face's state (after an x face
+            // only a y reflection applies)
+#pragma unroll 1
+            for (int r = 0; r < RC; r++) {
+                const unsigned io = (flips >> (16 + 3 * r)) & 7u;
+                if (ccode[r] < 0 || io == 0) continue;
+                const int li = tid + r * NT;
+                const bool fly = io < 3 && ((flips >> (2 * r)) & 2u);
+#pragma unroll 1
+                for (int f = 0; f < NF; f++) {
+                    const T v = inflow_value<T>(ctrl, io - 1, inflow_component<NDIM>(f));
+                    sf[f][li] = (f == 2 && fly) ? -v : v;
+                }
+            }
+        }
+    };
+    (void)fix_cross;
 
     for (int m = m_beg; m < m_end; ++m) {
         const int k = NDIM == 3 ? m - 3 : 0;
@@ -945,7 +997,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
 
         if constexpr (NDIM == 3) {
             // own column, plane m, every field: z parabola of cell m-2
-            Parab<T> pnew[NF];
+            Prof pnew[NF];
 #pragma unroll
             for (int f = 0; f < NF; f++) {
                 T v = ov[f];
@@ -955,11 +1007,20 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                 q2[f] = v;
                 const T dnew = limited_slope(q0[f], q1[f], q2[f]);
                 const T qInew = interface_value(q0[f], q1[f], dmq[f], dnew);
+#ifdef PPML_EXACT
                 pnew[f] = profile(gp.first_order, q0[f], qI[f], qInew);
+#else
+                pnew[f] = mono_edges(gp.first_order, q0[f], qI[f], qInew);
+#endif
                 dmq[f] = dnew;
                 qI[f] = qInew;
             }
             sz0 = sz1; sz1 = sz2; sz2 = sz3; sz3 = dsqrt(q2[0]);
+            // the cross tile of plane k, sent one plane ago, is completed
+            // before the barrier below, which also orders it for the x / y
+            // jobs of the plane
+            if constexpr (PIPE)
+                if (k >= z0) fix_cross(k);
             if (need_vel) {
                 __syncthreads();
                 // transverse velocity of the own column at plane m-2
@@ -971,15 +1032,25 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                 const T vh = interface_velocity(vtz_prev, sz0, vt, sz1);
 #ifdef PPML_EXACT
                 const T z = dabs(vh) * tau / hz;
-#else
-                const T z = dabs(vh) * tohz;
-#endif
 #pragma unroll
                 for (int f = 0; f < NF; f++) {
                     const T F = upwind_flux(vh, z, pprev[f], pnew[f]);
-                    DFz[f] = PPML_DIV(F - Fzp[f], hz, ihz);
+                    DFz[f] = (F - Fzp[f]) / hz;
                     Fzp[f] = F;
                 }
+#else
+                // fluxes times tau / h_z: the update subtracts their differences
+                const T vs = vh * tohz;
+                const StripW<T> w = strip_weights(dabs(vs));
+                const bool up = vh >= T(0);
+#pragma unroll
+                for (int f = 0; f < NF; f++) {
+                    const Prof &a = pprev[f], &b = pnew[f];
+                    const T F = vs * strip_mean(w, up ? a.R : b.L, up ? a.L : b.R, up ? a.C : b.C);
+                    DFz[f] = F - Fzp[f];
+                    Fzp[f] = F;
+                }
+#endif
                 vtz_prev = vt;
             }
 #pragma unroll
@@ -1022,38 +1093,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
             // the previous pass reads its tile (own cell values) after its last
             // barrier: every wave must be done before the tile is overwritten
             if (pass > 0) __syncthreads();
-            if constexpr (PIPE) {
-                // the cross tile of plane k was sent to LDS one plane ago:
-                // wait for this wave's transfers, then mirror the normal
-                // momenta at reflecting faces
-                __builtin_amdgcn_s_waitcnt(VMCNT0);
-                if (flips & 0xFFFFu) {
-#pragma unroll
-                    for (int r = 0; r < RC; r++) {
-                        if (ccode[r] < 0) continue;
-                        const int li = tid + r * NT;
-                        const unsigned fl = flips >> (2 * r);
-                        if (fl & 1) sf[1][li] = -sf[1][li];
-                        if (NDIM >= 2 && (fl & 2)) sf[2][li] = -sf[2][li];
-                    }
-                }
-                if (gp.any_inflow) {
-                    // ghosts of inflow faces take the face's state (after an x
-                    // face only a y reflection applies)
-#pragma unroll 1
-                    for (int r = 0; r < RC; r++) {
-                        const unsigned io = (flips >> (16 + 3 * r)) & 7u;
-                        if (ccode[r] < 0 || io == 0) continue;
-                        const int li = tid + r * NT;
-                        const bool fly = io < 3 && ((flips >> (2 * r)) & 2u);
-#pragma unroll 1
-                        for (int f = 0; f < NF; f++) {
-                            const T v = inflow_value<T>(ctrl, io - 1, inflow_component<NDIM>(f));
-                            sf[f][li] = (f == 2 && fly) ? -v : v;
-                        }
-                    }
-                }
-            } else {
+            if constexpr (!PIPE) {
                 // cross tiles of the pass's fields
 #pragma unroll
                 for (int r = 0; r < RC; r++) {
@@ -1089,13 +1129,14 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                         }
                     }
                 }
+                __syncthreads();
             }
-            __syncthreads();
             // interface values (Appendix step 1) at every face of the tile.  In
             // FP64, two neighbouring faces per job share the limited slope of
             // the cell between them (3 slopes for 2 faces; the last job of a
             // row or column may hold one face); the FP32 kernel, at its
-            // register limit, takes one face per job.
+            // register limit, takes one cell per job and shares slopes between
+            // neighbouring lanes.
             if constexpr (sizeof(T) == 8) {
                 constexpr int PXR = (TX + 4) / 2;             // x jobs per row
                 constexpr int PYC = (TY + 4) / 2;             // y jobs per column
@@ -1131,41 +1172,78 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                             const T *q = sf[g];
                             const T da = limited_slope(q[l], q[l + PW], q[l + 2 * PW]);
                             const T db = limited_slope(q[l + PW], q[l + 2 * PW], q[l + 3 * PW]);
-                            s_qy[g][fyi * TX + cx] = interface_value(q[l + PW], q[l + 2 * PW], da, db);
+                            s_qy[g][cx * (TY + 3) + fyi] = interface_value(q[l + PW], q[l + 2 * PW], da, db);
                             if (two) {
                                 const T dc = limited_slope(q[l + 2 * PW], q[l + 3 * PW], q[l + 4 * PW]);
-                                s_qy[g][(fyi + 1) * TX + cx] = interface_value(q[l + 2 * PW], q[l + 3 * PW], db, dc);
+                                s_qy[g][cx * (TY + 3) + fyi + 1] = interface_value(q[l + 2 * PW], q[l + 3 * PW], db, dc);
                             }
                         }
                     }
                 }
             } else {
-                using JQ = JobMap<NT, NXQ, NYQ>;
+                // One job per cell of a row (x) or column (y) of the tile and
+                // its halo: the lane takes the limited slope of its cell, the
+                // slope of the previous cell of the line from the previous
+                // lane of its 16-lane DPP row, and writes the interface value
+                // between the two cells.  Lane 0 of each DPP row only supplies
+                // the slope of the cell before the row's first cell, so every
+                // slope is computed once per 15 faces rather than twice per
+                // face.  x cells: tile-rel x -2 .. TX+1 (x fastest) of rows
+                // 0 .. TY-1; y cells: tile-rel y -2 .. TY+1 (y fastest) of
+                // columns 0 .. TX-1.
+                constexpr int NXC = (TX + 4) * TY;
+                constexpr int NYC = NDIM >= 2 ? TX * (TY + 4) : 0;
+                constexpr int DX = (NXC + 14) / 15;  // DPP rows of x cells
+                constexpr int DY = (NYC + 14) / 15;
+                using JD = JobMap<NT, DX * 16, DY * 16>;
+                const int t = ln & 15;
 #pragma unroll 1
-                for (int rq = 0; rq < JQ::R; rq++) {
-                    const int j = JQ::job(rq, wv, ln);
-                    if (j < NXQ) {
-                        const int fxi = j % (TX + 3), cy = j / (TX + 3);
-                        const int l = (cy + HY) * PW + fxi;  // q of tile-rel cells fxi-3 .. fxi
+                for (int rq = 0; rq < JD::R; rq++) {
+                    const int jd = JD::job(rq, wv, ln);  // DPP-row slot: row jd >> 4, lane t
+                    if (jd >= (DX + DY) * 16) continue;  // whole DPP rows past the last one of a kind
+                    if (jd < DX * 16) {
+                        const int X = (jd >> 4) * 15 + t - 1;
+                        const int Xc = X < 0 ? 0 : (X < NXC ? X : NXC - 1);
+                        const int c = Xc % (TX + 4) - 2, cy = Xc / (TX + 4);
+                        const int l = (cy + HY) * PW + c + HX;
+                        const bool put = t >= 1 && X < NXC && c > -2;
+                        const int o = cy * (TX + 3) + c + 1;  // face between cells c-1 and c
+                        // every field's values and faces first, the stores
+                        // after them, so that no load waits behind a store
+                        T iv[G];
 #pragma unroll
                         for (int g = 0; g < G; g++) {
                             if (f0 + g >= NF) break;
                             const T *q = sf[g];
-                            const T da = limited_slope(q[l], q[l + 1], q[l + 2]);
-                            const T db = limited_slope(q[l + 1], q[l + 2], q[l + 3]);
-                            s_qx[g][j] = interface_value(q[l + 1], q[l + 2], da, db);
+                            const T qm = q[l - 1], q0 = q[l];
+                            const T d = limited_slope(qm, q0, q[l + 1]);
+                            iv[g] = interface_value(qm, q0, dpp_prev16(d), d);
                         }
-                    } else if (NDIM >= 2 && j < NXQ + NYQ) {
-                        const int jj = j - NXQ;
-                        const int cx = jj % TX, fyi = jj / TX;
-                        const int l = fyi * PW + cx + HX;  // rows fyi-3 .. fyi (tile-rel)
+                        if (put) {
+#pragma unroll
+                            for (int g = 0; g < G; g++)
+                                if (f0 + g < NF) s_qx[g][o] = iv[g];
+                        }
+                    } else if constexpr (NDIM >= 2) {
+                        const int Y = ((jd >> 4) - DX) * 15 + t - 1;
+                        const int Yc = Y < 0 ? 0 : (Y < NYC ? Y : NYC - 1);
+                        const int r = Yc % (TY + 4) - 2, cx = Yc / (TY + 4);
+                        const int l = (r + HY) * PW + cx + HX;
+                        const bool put = t >= 1 && Y < NYC && r > -2;
+                        const int o = cx * (TY + 3) + r + 1;  // face between rows r-1 and r
+                        T iv[G];
 #pragma unroll
                         for (int g = 0; g < G; g++) {
                             if (f0 + g >= NF) break;
                             const T *q = sf[g];
-                            const T da = limited_slope(q[l], q[l + PW], q[l + 2 * PW]);
-                            const T db = limited_slope(q[l + PW], q[l + 2 * PW], q[l + 3 * PW]);
-                            s_qy[g][jj] = interface_value(q[l + PW], q[l + 2 * PW], da, db);
+                            const T qm = q[l - PW], q0 = q[l];
+                            const T d = limited_slope(qm, q0, q[l + PW]);
+                            iv[g] = interface_value(qm, q0, dpp_prev16(d), d);
+                        }
+                        if (put) {
+#pragma unroll
+                            for (int g = 0; g < G; g++)
+                                if (f0 + g < NF) s_qy[g][o] = iv[g];
                         }
                     }
                 }
@@ -1209,9 +1287,6 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                     const int lf = cy * (TX + 3) + u + 1;         // its left face
 #ifdef PPML_EXACT
                     const T z = dabs(vh) * tau / hx;
-#else
-                    const T z = dabs(vh) * tohx;
-#endif
 #pragma unroll
                     for (int g = 0; g < G; g++) {
                         if (f0 + g >= NF) break;
@@ -1219,6 +1294,16 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                         const T fs = left ? avg_left(p.L, p.R, p.Q6, z) : avg_right(p.L, p.R, p.Q6, z);
                         Fr[r][g] = vh * fs;
                     }
+#else
+                    const T vs = vh * tohx;  // fluxes times tau / h_x
+                    const StripW<T> w = strip_weights(dabs(vs));
+#pragma unroll
+                    for (int g = 0; g < G; g++) {
+                        if (f0 + g >= NF) break;
+                        const Edges<T> e = mono_edges(gp.first_order, sf[g][lq], s_qx[g][lf], s_qx[g][lf + 1]);
+                        Fr[r][g] = vs * strip_mean(w, left ? e.R : e.L, left ? e.L : e.R, e.C);
+                    }
+#endif
                 } else if (NDIM >= 2 && j < NXI + NYI) {
                     const int jj = j - NXI;
                     const int cx = jj % TX, iy = jj / TX;
@@ -1244,19 +1329,26 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                     const bool left = vh >= T(0);
                     const int u = left ? iy - 1 : iy;
                     const int lq = (u + HY) * PW + cx + HX;
-                    const int lf = (u + 1) * TX + cx;
+                    const int lf = cx * (TY + 3) + u + 1;
 #ifdef PPML_EXACT
                     const T z = dabs(vh) * tau / hy;
-#else
-                    const T z = dabs(vh) * tohy;
-#endif
 #pragma unroll
                     for (int g = 0; g < G; g++) {
                         if (f0 + g >= NF) break;
-                        const Parab<T> p = profile(gp.first_order, sf[g][lq], s_qy[g][lf], s_qy[g][lf + TX]);
+                        const Parab<T> p = profile(gp.first_order, sf[g][lq], s_qy[g][lf], s_qy[g][lf + 1]);
                         const T fs = left ? avg_left(p.L, p.R, p.Q6, z) : avg_right(p.L, p.R, p.Q6, z);
                         Fr[r][g] = vh * fs;
                     }
+#else
+                    const T vs = vh * tohy;  // fluxes times tau / h_y
+                    const StripW<T> w = strip_weights(dabs(vs));
+#pragma unroll
+                    for (int g = 0; g < G; g++) {
+                        if (f0 + g >= NF) break;
+                        const Edges<T> e = mono_edges(gp.first_order, sf[g][lq], s_qy[g][lf], s_qy[g][lf + 1]);
+                        Fr[r][g] = vs * strip_mean(w, left ? e.R : e.L, left ? e.L : e.R, e.C);
+                    }
+#endif
                 }
             }
             __syncthreads();
@@ -1279,8 +1371,14 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                 const int f = f0 + g;
                 if (f >= NF) break;
                 own[f] = sf[g][(ty + HY) * PW + tx + HX];
-                T a = PPML_DIV(s_Fx[g][ty * (TX + 1) + tx + 1] - s_Fx[g][ty * (TX + 1) + tx], hx, ihx);
-                if constexpr (NDIM >= 2) a = a + PPML_DIV(s_Fy[g][(ty + 1) * TX + tx] - s_Fy[g][ty * TX + tx], hy, ihy);
+#ifdef PPML_EXACT
+                T a = (s_Fx[g][ty * (TX + 1) + tx + 1] - s_Fx[g][ty * (TX + 1) + tx]) / hx;
+                if constexpr (NDIM >= 2) a = a + (s_Fy[g][(ty + 1) * TX + tx] - s_Fy[g][ty * TX + tx]) / hy;
+#else
+                // (the product build's fluxes carry the factor tau / h)
+                T a = s_Fx[g][ty * (TX + 1) + tx + 1] - s_Fx[g][ty * (TX + 1) + tx];
+                if constexpr (NDIM >= 2) a = a + (s_Fy[g][(ty + 1) * TX + tx] - s_Fy[g][ty * TX + tx]);
+#endif
                 if constexpr (NDIM == 3) a = a + DFz[f];
                 acc[f] = a;
             }
@@ -1297,7 +1395,12 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
             const int c = k * plane + gy * nx + gx;
             T fn[NF];
 #pragma unroll
-            for (int f = 0; f < NF; f++) fn[f] = own[f] - tau * acc[f];
+            for (int f = 0; f < NF; f++)
+#ifdef PPML_EXACT
+                fn[f] = own[f] - tau * acc[f];
+#else
+                fn[f] = own[f] - acc[f];
+#endif
             // total-energy correction (Sec. 2.4), FP64 arithmetic
             const double r = (double)fn[0];
             double mx = (double)fn[1];
@@ -1345,8 +1448,10 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
 
 // Waves per SIMD the register allocator aims for in the Lagrangian kernel:
 // three 4-wave work groups per CU (<= 168 VGPRs) for the FP32 3-D kernel,
-// whose LDS tiles also fit three times; the compiler's choice otherwise.
-template <typename T, int NDIM> constexpr int lagr_waves() { return (sizeof(T) == 4 && NDIM == 3) ? 3 : 1; }
+// whose LDS tiles also fit three times; two (<= 256 registers, so that no
+// accumulation register halves the occupancy) for the FP64 3-D kernel; the
+// compiler's choice otherwise.
+template <typename T, int NDIM> constexpr int lagr_waves() { return NDIM == 3 ? (sizeof(T) == 4 ? 3 : 2) : 1; }
 
 template <typename T, int NDIM, int TX, int TY, int G>
 __global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(lagr_waves<T, NDIM>()))) void k_lagr(const T *__restrict__ Wst, T *__restrict__ U, GridParams gp,
