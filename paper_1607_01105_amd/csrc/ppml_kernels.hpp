@@ -405,14 +405,50 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
     for (int m = m_beg; m < m_end; ++m) {
         const int k = NDIM == 3 ? m - 3 : 0;
         T DPz = 0, DPVz = 0, DVz = 0;
+        // FP32: every load of the iteration is issued before any of its
+        // values is used, so that the iteration costs one memory latency:
+        // the own column at plane m (3-D), then, past the warm-up planes, the
+        // cross tile of plane k (lanes without a cross cell load their own
+        // cell) and the own cell of plane k for the update.  FP64, whose
+        // registers are scarcer, issues the cross tile after the z arithmetic
+        // and the own cell in the update.
+        constexpr bool EARLY = sizeof(T) == 4;
+        const bool live = k >= z0;
+        int fz = 0;
+        T zr[3] = {T(1), T(1), T(1)};  // rho, m_z, rho*eps of the column at plane m
         if constexpr (NDIM == 3) {
-            int fz;
             const int mz = map_index(m, nz, gp.bc_lo[2], gp.bc_hi[2], fz);
             const int c = mz * plane + cy_ * nx + cx_;
-            T rho = Uf[0][c];
-            T mzv = Uf[3][c];
+            zr[0] = Uf[0][c];
+            zr[1] = Uf[3][c];
+            zr[2] = Uf[5][c];
+        }
+        T xr[RC][NDIM + 2];  // rho, m_x, (m_y), rho*eps
+        T uo[NF];            // U^n of the own cell
+        auto load_cross = [&]() {
+#pragma unroll
+            for (int r = 0; r < RC; r++) {
+                const int c = k * plane + (ccode[r] >= 0 ? ccode[r] : own_off);
+                xr[r][0] = Uf[0][c];
+                xr[r][1] = Uf[1][c];
+                if constexpr (NDIM >= 2) xr[r][2] = Uf[2][c];
+                xr[r][NDIM + 1] = Uf[2 + NDIM][c];
+            }
+        };
+        auto load_own = [&]() {
+            const int c = k * plane + gy * nx + gx;
+#pragma unroll
+            for (int f = 0; f < NF; f++) uo[f] = Uf[f][c];
+        };
+        if (EARLY && live) {
+            load_cross();
+            if (valid) load_own();
+        }
+        if constexpr (NDIM == 3) {
+            T rho = zr[0];
+            T mzv = zr[1];
             if (fz) mzv = -mzv;
-            T e = Uf[5][c];
+            T e = zr[2];
             if (gp.any_inflow) {  // plane m is a ghost of an inflow z face
                 const int fzi = inflow_face(m, nz, gp.bc_lo[2], gp.bc_hi[2], 2);
                 if (fzi >= 0) {
@@ -454,17 +490,7 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
         }
 
         // ---- x / y directions of plane k from LDS ----
-        // every round's loads first, so that the tile costs one memory
-        // latency; lanes without a cross cell load their own cell
-        T xr[RC][NDIM + 2];  // rho, m_x, (m_y), rho*eps
-#pragma unroll
-        for (int r = 0; r < RC; r++) {
-            const int c = k * plane + (ccode[r] >= 0 ? ccode[r] : own_off);
-            xr[r][0] = Uf[0][c];
-            xr[r][1] = Uf[1][c];
-            if constexpr (NDIM >= 2) xr[r][2] = Uf[2][c];
-            xr[r][NDIM + 1] = Uf[2 + NDIM][c];
-        }
+        if constexpr (!EARLY) load_cross();
         // overlaid tiles: the previous plane's update has read its interface
         // states before they are overwritten (the loads above are in flight)
         if constexpr (OVERLAY) __syncthreads();
@@ -607,13 +633,14 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
                 sV = sV + DVz;
             }
             const int c = k * plane + gy * nx + gx;
-            const T rho = Uf[0][c];
+            if constexpr (!EARLY) load_own();
+            const T rho = uo[0];
             T mom[3];
-            mom[0] = Uf[1][c];
-            mom[1] = NDIM >= 2 ? Uf[2][c] : T(0);
-            mom[2] = NDIM >= 3 ? Uf[3][c] : T(0);
-            const T Et = Uf[1 + NDIM][c];
-            const T e = Uf[2 + NDIM][c];
+            mom[0] = uo[1];
+            mom[1] = NDIM >= 2 ? uo[2] : T(0);
+            mom[2] = NDIM >= 3 ? uo[3] : T(0);
+            const T Et = uo[1 + NDIM];
+            const T e = uo[2 + NDIM];
             T mn[3];
             mn[0] = mom[0] - tau * DPx;
             mn[1] = mom[1] - tau * DPy;
@@ -640,9 +667,15 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
     }
 }
 
+// Waves per SIMD the register allocator aims for in the Eulerian kernel
+// without self-gravity: four (<= 128 VGPRs) for FP32 3-D, three (<= 168)
+// for FP64 3-D where its LDS tiles fit that many groups; the compiler's
+// choice otherwise.
+template <typename T, int NDIM, int XF> constexpr int euler_waves() { return NDIM == 3 && XF == 0 ? (sizeof(T) == 4 ? 4 : 3) : 1; }
+
 template <typename T, int NDIM, int TX, int TY, int XF = 0>
-__global__ __launch_bounds__(TX *TY) void k_euler(const T *__restrict__ U, T *__restrict__ Wst, GridParams gp,
-                                                   Ctrl *ctrl)
+__global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(euler_waves<T, NDIM, XF>()))) void k_euler(
+    const T *__restrict__ U, T *__restrict__ Wst, GridParams gp, Ctrl *ctrl)
 {
     int bx, by, bz;
     block_tile(gp, bx, by, bz);
@@ -1489,7 +1522,8 @@ __device__ __forceinline__ int batch_entry(const BatchEntry *__restrict__ ents, 
 }
 
 template <typename T, int NDIM, int TX, int TY>
-__global__ __launch_bounds__(TX *TY) void k_euler_batch(const BatchEntry *__restrict__ ents, int ne)
+__global__ __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(euler_waves<T, NDIM, 0>()))) void k_euler_batch(
+    const BatchEntry *__restrict__ ents, int ne)
 {
     const BatchEntry *e = ents + batch_entry(ents, ne, blockIdx.x);
     const int L = blockIdx.x - e->tile0;
