@@ -196,7 +196,11 @@ int ppml_get_time(ppml_grid *g, double *t, double *dt_last, int64_t *steps);
 /* Synchronize and read the current maxima of |v| and of c over the cells. */
 int ppml_max_speeds(ppml_grid *g, double *vmax, double *cmax);
 
-/* Synchronize and copy one conserved field to host_out (FP64, cells values).
+/* Synchronize and copy one conserved field to host_out (FP64, cells values):
+ * field 0 rho, 1 .. 3 rho v (x, y, z), 4 rho E, 5 rho eps -- the densities
+ * the scheme of Sec. 2 evolves, rho eps being the internal energy carried
+ * beside the total for the correction of Sec. 2.4.  Layout as for the
+ * setters: interior cells, C order [z][y][x].
  * Errors: PPML_EINVAL (field of an unused axis), PPML_ENOMEM, PPML_EHIP. */
 int ppml_get_conserved(ppml_grid *g, int32_t field, double *host_out);
 
@@ -208,11 +212,15 @@ int ppml_get_conserved(ppml_grid *g, int32_t field, double *host_out);
 int ppml_get_potential(ppml_grid *g, double *host_out);
 
 /* Synchronize and return the FP64 sums over all cells of the six conserved
- * densities (unused momentum axes give 0); the summation order is fixed,
- * so repeated calls on the same state give identical bits. */
+ * densities (unused momentum axes give 0): the totals of mass, momentum and
+ * total energy whose conservation the divergence form of Sec. 2 gives on
+ * periodic grids (Sec. 2.4 discusses the total-energy one).  The summation
+ * order is fixed, so repeated calls on the same state give identical bits. */
 int ppml_totals(ppml_grid *g, double out[6]);
 
-/* Synchronize the grid's stream; PPML_ENONFINITE if a step failed. */
+/* Synchronize the grid's stream; PPML_ENONFINITE if a step produced a
+ * non-physical state (rho <= 0 or eps <= 0 after the energy correction of
+ * Sec. 2.4) or a non-finite value. */
 int ppml_sync(ppml_grid *g);
 
 /* Destroy the host object (does not free caller memory). */

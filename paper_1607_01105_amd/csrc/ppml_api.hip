@@ -1335,10 +1335,12 @@ int ppml_batch_create(int32_t capacity, size_t budget_bytes, void *hip_stream, p
 {
     if (!out) return fail(PPML_EINVAL, "out is NULL");
     if (capacity < 1 || capacity > 65536) return fail(PPML_EINVAL, "capacity must be in [1, 65536]");
+    int device = 0;
+    HIPCHK(hipGetDevice(&device));
     ppml_batch *b = new (std::nothrow) ppml_batch();
     if (!b) return fail(PPML_ENOMEM, "host allocation failed");
     b->stream = (hipStream_t)hip_stream;
-    HIPCHK(hipGetDevice(&b->device));
+    b->device = device;
     b->capacity = capacity;
     b->budget = budget_bytes;
     b->in_use = 0;

@@ -405,14 +405,15 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
     for (int m = m_beg; m < m_end; ++m) {
         const int k = NDIM == 3 ? m - 3 : 0;
         T DPz = 0, DPVz = 0, DVz = 0;
-        // FP32: every load of the iteration is issued before any of its
-        // values is used, so that the iteration costs one memory latency:
-        // the own column at plane m (3-D), then, past the warm-up planes, the
-        // cross tile of plane k (lanes without a cross cell load their own
-        // cell) and the own cell of plane k for the update.  FP64, whose
-        // registers are scarcer, issues the cross tile after the z arithmetic
-        // and the own cell in the update.
-        constexpr bool EARLY = sizeof(T) == 4;
+        // FP32 without self-gravity: every load of the iteration is issued
+        // before any of its values is used, so that the iteration costs one
+        // memory latency: the own column at plane m (3-D), then, past the
+        // warm-up planes, the cross tile of plane k (lanes without a cross
+        // cell load their own cell) and the own cell of plane k for the
+        // update.  FP64 and the self-gravity kernels, whose registers are
+        // scarcer, issue the cross tile after the z arithmetic and the own
+        // cell in the update.
+        constexpr bool EARLY = sizeof(T) == 4 && XF == 0;
         const bool live = k >= z0;
         int fz = 0;
         T zr[3] = {T(1), T(1), T(1)};  // rho, m_z, rho*eps of the column at plane m

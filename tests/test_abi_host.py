@@ -188,6 +188,37 @@ def test_autotune_pick_prefers_fastest_then_default():
     assert pick({2: 0.3, 1: 0.3, 3: 0.9}) == 1
 
 
+def test_autotune_results_persist_per_device_and_build(tmp_path, monkeypatch):
+    """The persisted tile choices: a result stored for one device, library
+    build and workload comes back (integer tile indices included) for the
+    same three only; a damaged file reads as empty; an empty
+    PPML_AUTOTUNE_CACHE turns persistence off."""
+    from paper_1607_01105_amd import autotune as A
+
+    path = str(tmp_path / "sub" / "autotune.json")
+    grid_key = ("grid", "box", 3, (64, 64, 64), "fp32")
+    res = {"tile": 2, "shape": (16, 16), "ms_per_step": {0: 1.5, 1: 1.7, 2: 1.25, 3: 1.9}}
+    A.persisted_put(grid_key, res, "devA", "libX", path)
+    assert A.persisted_get(grid_key, "devA", "libX", path) == res
+    assert A.persisted_get(grid_key, "devB", "libX", path) is None
+    assert A.persisted_get(grid_key, "devA", "libY", path) is None
+    assert A.persisted_get(("grid", "box", 3, (64, 64, 32), "fp32"), "devA", "libX", path) is None
+    batch_key = ("batch", "fp32", ((1, (100,)), (2, (32, 48))))
+    bres = {1: {"tile": 0, "shape": (128, 1), "ms_per_step": {0: 0.1, 1: 0.2}},
+            2: {"tile": 1, "shape": (32, 8), "ms_per_step": {0: 0.3, 1: 0.2}}}
+    A.persisted_put(batch_key, bres, "devA", "libX", path)
+    assert A.persisted_get(batch_key, "devA", "libX", path) == bres
+    assert A.persisted_get(grid_key, "devA", "libX", path) == res  # both kept
+    with open(path, "w") as f:
+        f.write("{not json")
+    assert A.persisted_get(grid_key, "devA", "libX", path) is None
+    monkeypatch.setenv("PPML_AUTOTUNE_CACHE", "")
+    assert A.cache_path() is None
+    A.persisted_put(grid_key, res, "devA", "libX", A.cache_path())  # a no-op
+    monkeypatch.setenv("PPML_AUTOTUNE_CACHE", path)
+    assert A.cache_path() == path
+
+
 def test_inflow_descriptor_accepted(lib):
     from paper_1607_01105_amd import ppml
 
