@@ -242,6 +242,15 @@ template <typename T> __device__ __forceinline__ Parab<T> monotonize(T c, T l, T
     return p;
 }
 
+// The first-order scheme's constant state (Sec. 2.1) in place of the
+// parabola p of a cell of value c.  Selected after the parabola is built, so
+// that the choice is a select rather than a branch between the fields.
+template <typename T> __device__ __forceinline__ Parab<T> pick_profile(int first_order, T c, const Parab<T> &p)
+{
+    const bool fo = first_order != 0;
+    return Parab<T>{fo ? c : p.L, fo ? c : p.R, fo ? T(0) : p.Q6};
+}
+
 // Full parabola of the middle cell of five consecutive values.
 template <typename T> __device__ __forceinline__ Parab<T> parabola5(T qm2, T qm1, T q0, T qp1, T qp2)
 {
@@ -261,11 +270,6 @@ template <typename T>
 __device__ __forceinline__ void parabola_pair(int first_order, T qm2, T qm1, T q0, T q1, T q2, T q3, Parab<T> &a,
                                               Parab<T> &b)
 {
-    if (first_order) {
-        a = Parab<T>{q0, q0, T(0)};
-        b = Parab<T>{q1, q1, T(0)};
-        return;
-    }
     const T sm = limited_slope(qm2, qm1, q0);
     const T s0 = limited_slope(qm1, q0, q1);
     const T s1 = limited_slope(q0, q1, q2);
@@ -273,21 +277,19 @@ __device__ __forceinline__ void parabola_pair(int first_order, T qm2, T qm1, T q
     const T il = interface_value(qm1, q0, sm, s0);  // left edge of cell 0
     const T ic = interface_value(q0, q1, s0, s1);   // between the cells
     const T ir = interface_value(q1, q2, s1, s2);   // right edge of cell 1
-    a = monotonize(q0, il, ic);
-    b = monotonize(q1, ic, ir);
+    a = pick_profile(first_order, q0, monotonize(q0, il, ic));
+    b = pick_profile(first_order, q1, monotonize(q1, ic, ir));
 }
 
 // State profile of a cell: the monotonised parabola, or the constant cell
 // value in the first-order scheme.
 template <typename T> __device__ __forceinline__ Parab<T> profile(int first_order, T c, T l, T r)
 {
-    if (first_order) return Parab<T>{c, c, T(0)};
-    return monotonize(c, l, r);
+    return pick_profile(first_order, c, monotonize(c, l, r));
 }
 template <typename T> __device__ __forceinline__ Parab<T> profile5(int first_order, T qm2, T qm1, T q0, T qp1, T qp2)
 {
-    if (first_order) return Parab<T>{q0, q0, T(0)};
-    return parabola5(qm2, qm1, q0, qp1, qp2);
+    return pick_profile(first_order, q0, parabola5(qm2, qm1, q0, qp1, qp2));
 }
 
 // Appendix: mean of a cell's parabola over the strip of z*h next to its
@@ -382,10 +384,11 @@ template <typename T> struct Edges {
 };
 template <typename T> __device__ __forceinline__ Edges<T> mono_edges(int first_order, T c, T l, T r)
 {
-    if (first_order) return Edges<T>{c, c, c};
-    // the rules of monotonize, in terms of the one-sided jumps
+    // the rules of monotonize, in terms of the one-sided jumps; the
+    // first-order scheme's constant state is the flattened profile (folded
+    // into the same selects, so that no branch splits the fields' loads)
     const T dl = c - l, dr = r - c;
-    const bool flat = dl * dr <= T(0);
+    const bool flat = first_order != 0 || dl * dr <= T(0);
     const T L = flat ? c : (dabs(dl) > K<T>::two * dabs(dr) ? c - K<T>::two * dr : l);
     const T R = flat ? c : (dabs(dr) > K<T>::two * dabs(dl) ? c + K<T>::two * dl : r);
     return Edges<T>{L, R, c};
