@@ -472,7 +472,7 @@ def pin_aksenov(lib=None, small_cfl=True):
     assert 0.8 < T < 1.4, T
     if small_cfl:
         T_small = math.log2(_aksenov_err(314, 0.0125, lib) / _aksenov_err(628, 0.0125, lib))
-        assert abs(T_small - printed("aksenov_order_T")) < 0.3, T_small
+        assert abs(T_small - printed("aksenov_order_T")) < 0.1, T_small
 
 
 def pin_aksenov_internal_energy_path(lib=None):
