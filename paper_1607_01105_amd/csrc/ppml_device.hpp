@@ -242,6 +242,29 @@ template <typename T> __device__ __forceinline__ Parab<T> monotonize(T c, T l, T
     return p;
 }
 
+// Product build: of a cell's monotonised parabola the Lagrangian stage needs
+// only the two edge values and the cell value (the curvature coefficient is
+// 6 c - 3 (L + R)), and of the mean over the strip of width z h next to an
+// interface only the weights of the upwind cell's near edge, far edge and
+// value.  Expanding either strip mean (avg_left, avg_right below) with that
+// coefficient gives
+//   (1 - z)^2 near + z (z - 1) far + z (3 - 2 z) c,
+// weights that depend on z alone and serve every field of the interface.
+template <typename T> struct Edges {
+    T L, R, C;
+};
+template <typename T> __device__ __forceinline__ Edges<T> mono_edges(int first_order, T c, T l, T r)
+{
+    // the rules of monotonize, in terms of the one-sided jumps; the
+    // first-order scheme's constant state is the flattened profile (folded
+    // into the same selects, so that no branch splits the fields' loads)
+    const T dl = c - l, dr = r - c;
+    const bool flat = first_order != 0 || dl * dr <= T(0);
+    const T L = flat ? c : (dabs(dl) > K<T>::two * dabs(dr) ? c - K<T>::two * dr : l);
+    const T R = flat ? c : (dabs(dr) > K<T>::two * dabs(dl) ? c + K<T>::two * dl : r);
+    return Edges<T>{L, R, c};
+}
+
 // The first-order scheme's constant state (Sec. 2.1) in place of the
 // parabola p of a cell of value c.  Selected after the parabola is built, so
 // that the choice is a select rather than a branch between the fields.
@@ -251,45 +274,40 @@ template <typename T> __device__ __forceinline__ Parab<T> pick_profile(int first
     return Parab<T>{fo ? c : p.L, fo ? c : p.R, fo ? T(0) : p.Q6};
 }
 
-// Full parabola of the middle cell of five consecutive values.
-template <typename T> __device__ __forceinline__ Parab<T> parabola5(T qm2, T qm1, T q0, T qp1, T qp2)
-{
-    T dmm = limited_slope(qm2, qm1, q0);
-    T dm0 = limited_slope(qm1, q0, qp1);
-    T dmp = limited_slope(q0, qp1, qp2);
-    T l = interface_value(qm1, q0, dmm, dm0);
-    T r = interface_value(q0, qp1, dm0, dmp);
-    return monotonize(q0, l, r);
-}
-
-// Parabolas of two neighbouring cells q0, q1 of a line (values qm2 .. q3),
-// sharing the slopes and the interface value between them: each parabola is
-// computed by the same operations as parabola5 of its cell.  Constant states
-// in the first-order scheme.
-template <typename T>
-__device__ __forceinline__ void parabola_pair(int first_order, T qm2, T qm1, T q0, T q1, T q2, T q3, Parab<T> &a,
-                                              Parab<T> &b)
-{
-    const T sm = limited_slope(qm2, qm1, q0);
-    const T s0 = limited_slope(qm1, q0, q1);
-    const T s1 = limited_slope(q0, q1, q2);
-    const T s2 = limited_slope(q1, q2, q3);
-    const T il = interface_value(qm1, q0, sm, s0);  // left edge of cell 0
-    const T ic = interface_value(q0, q1, s0, s1);   // between the cells
-    const T ir = interface_value(q1, q2, s1, s2);   // right edge of cell 1
-    a = pick_profile(first_order, q0, monotonize(q0, il, ic));
-    b = pick_profile(first_order, q1, monotonize(q1, ic, ir));
-}
-
 // State profile of a cell: the monotonised parabola, or the constant cell
-// value in the first-order scheme.
+// value in the first-order scheme.  The product build takes the constant
+// state as a flattened cell (L = R = c gives Q6 = 0 exactly), so that no
+// select follows the parabola.
 template <typename T> __device__ __forceinline__ Parab<T> profile(int first_order, T c, T l, T r)
 {
+#ifdef PPML_EXACT
     return pick_profile(first_order, c, monotonize(c, l, r));
+#else
+    const Edges<T> e = mono_edges(first_order, c, l, r);
+    return Parab<T>{e.L, e.R, K<T>::six * (c - K<T>::half * (e.L + e.R))};
+#endif
 }
-template <typename T> __device__ __forceinline__ Parab<T> profile5(int first_order, T qm2, T qm1, T q0, T qp1, T qp2)
+
+// Parabolas of NC consecutive cells of a line, q[0], q[S], ..., q[(NC - 1) S]
+// (values q[-2 S] .. q[(NC + 1) S]), written to out[0], out[OS], ...: each
+// slope and interface value is built once and serves the cells on both of
+// its sides, and each parabola comes from its cell's three slopes and two
+// interface values by the same operations as on its own.  Constant states in
+// the first-order scheme.
+template <int NC, int S, int OS, typename T>
+__device__ __forceinline__ void parabola_run(int first_order, const T *q, Parab<T> *out)
 {
-    return pick_profile(first_order, q0, parabola5(qm2, qm1, q0, qp1, qp2));
+    T v[NC + 4];  // cells -2 .. NC + 1
+#pragma unroll
+    for (int i = 0; i < NC + 4; i++) v[i] = q[(i - 2) * S];
+    T sl[NC + 2];  // limited slopes of cells -1 .. NC
+#pragma unroll
+    for (int i = 0; i < NC + 2; i++) sl[i] = limited_slope(v[i], v[i + 1], v[i + 2]);
+    T iv[NC + 1];  // interface values between cells i - 1 and i, i = 0 .. NC
+#pragma unroll
+    for (int i = 0; i <= NC; i++) iv[i] = interface_value(v[i + 1], v[i + 2], sl[i], sl[i + 1]);
+#pragma unroll
+    for (int i = 0; i < NC; i++) out[i * OS] = profile(first_order, v[i + 2], iv[i], iv[i + 1]);
 }
 
 // Appendix: mean of a cell's parabola over the strip of z*h next to its
@@ -372,27 +390,6 @@ template <typename T> __device__ __forceinline__ T upwind_flux(T vh, T z, const 
     return vh * fs;
 }
 
-// Product build: of a cell's monotonised parabola the Lagrangian stage needs
-// only the two edge values and the cell value (the curvature coefficient is
-// 6 c - 3 (L + R)), and of the mean over the strip of width z h next to an
-// interface only the weights of the upwind cell's near edge, far edge and
-// value.  Expanding either strip mean above with that coefficient gives
-//   (1 - z)^2 near + z (z - 1) far + z (3 - 2 z) c,
-// weights that depend on z alone and serve every field of the interface.
-template <typename T> struct Edges {
-    T L, R, C;
-};
-template <typename T> __device__ __forceinline__ Edges<T> mono_edges(int first_order, T c, T l, T r)
-{
-    // the rules of monotonize, in terms of the one-sided jumps; the
-    // first-order scheme's constant state is the flattened profile (folded
-    // into the same selects, so that no branch splits the fields' loads)
-    const T dl = c - l, dr = r - c;
-    const bool flat = first_order != 0 || dl * dr <= T(0);
-    const T L = flat ? c : (dabs(dl) > K<T>::two * dabs(dr) ? c - K<T>::two * dr : l);
-    const T R = flat ? c : (dabs(dr) > K<T>::two * dabs(dl) ? c + K<T>::two * dl : r);
-    return Edges<T>{L, R, c};
-}
 template <typename T> struct StripW {
     T near, far, mid;
 };

@@ -266,10 +266,15 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
     constexpr int PS = PW * PH;
     constexpr int NXP = (TX + 2) * TY;
     constexpr int NYP = NDIM >= 2 ? TX * (TY + 2) : 1;
-    static_assert(TX % 2 == 0 && (NDIM < 2 || TY % 2 == 0), "parabola pairs need even tile extents");
-    constexpr int PXR = (TX + 2) / 2;                     // x pairs per row
-    constexpr int NXR = PXR * TY;                         // x pair jobs
-    constexpr int NYR = NDIM >= 2 ? TX * ((TY + 2) / 2) : 0;  // y pair jobs
+    // parabola jobs: runs of NC cells along x (rows of TX + 2 cells) or y
+    // (columns of TY + 2); a line's last run starts early where NC does not
+    // divide it, so it recomputes cells of the run before it (same values)
+    constexpr int NC = NDIM == 1 ? 2 : 5;
+    static_assert(TX + 2 >= NC && (NDIM < 2 || TY + 2 >= NC), "a run fits a line of the tile");
+    constexpr int RXN = (TX + 2 + NC - 1) / NC;               // x runs per row
+    constexpr int RYN = (TY + 2 + NC - 1) / NC;               // y runs per column
+    constexpr int NXR = RXN * TY;                             // x runs of a field
+    constexpr int NYR = NDIM >= 2 ? RYN * TX : 0;             // y runs of a field
     constexpr int NXI = (TX + 1) * TY;
     constexpr int NYI = NDIM >= 2 ? TX * (TY + 1) : 1;
 
@@ -562,32 +567,31 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
             }
         }
         __syncthreads();
-        // parabolas of v_d and p, two neighbouring cells per job (shared slopes
-        // and interface value): x pairs of each row, then y pairs of each
-        // column, in one job space
-        using JP = JobMap<NT, NXR, NYR>;
+        // parabolas of v_d and p, a run of NC cells of one field per job
+        // (slopes and interface values shared inside the run): x runs of each
+        // row (v_x, then p), then y runs of each column (v_y, then p), in one
+        // job space
+        using JP = JobMap<NT, 2 * NXR, 2 * NYR>;
 #pragma unroll 1
         for (int rq = 0; rq < JP::R; rq++) {
             const int j = JP::job(rq, wv, ln);
-            if (j < NXR) {
-                const int pr = j % PXR, cy = j / PXR;
-                const int cx = 2 * pr;  // first cell of the pair (tile-rel x = cx - 1)
+            if (j < 2 * NXR) {
+                const bool fp = j >= NXR;
+                const int jr = fp ? j - NXR : j;
+                const int rx = jr % RXN, cy = jr / RXN;
+                const int cx = NC * rx < TX + 2 - NC ? NC * rx : TX + 2 - NC;  // first cell (tile-rel x = cx - 1)
                 const int li = (cy + HY) * PW + cx + 2;
                 const int o = cy * (TX + 2) + cx;
-                parabola_pair(gp.first_order, s_vx[li - 2], s_vx[li - 1], s_vx[li], s_vx[li + 1], s_vx[li + 2],
-                              s_vx[li + 3], xv[o], xv[o + 1]);
-                parabola_pair(gp.first_order, s_p[li - 2], s_p[li - 1], s_p[li], s_p[li + 1], s_p[li + 2],
-                              s_p[li + 3], xp[o], xp[o + 1]);
-            } else if (NDIM >= 2 && j < NXR + NYR) {
-                const int jj = j - NXR;
-                const int cx = jj % TX, pr = jj / TX;
-                const int cy = 2 * pr;  // first cell of the pair (tile-rel y = cy - 1)
+                parabola_run<NC, 1, 1>(gp.first_order, (fp ? s_p : s_vx) + li, (fp ? xp : xv) + o);
+            } else if (NDIM >= 2 && j < 2 * (NXR + NYR)) {
+                const int jj = j - 2 * NXR;
+                const bool fp = jj >= NYR;
+                const int jr = fp ? jj - NYR : jj;
+                const int cx = jr % TX, ry = jr / TX;
+                const int cy = NC * ry < TY + 2 - NC ? NC * ry : TY + 2 - NC;  // first cell (tile-rel y = cy - 1)
                 const int li = (cy - 1 + HY) * PW + cx + HX;
                 const int o = cy * TX + cx;
-                parabola_pair(gp.first_order, s_vy[li - 2 * PW], s_vy[li - PW], s_vy[li], s_vy[li + PW],
-                              s_vy[li + 2 * PW], s_vy[li + 3 * PW], yv[o], yv[o + TX]);
-                parabola_pair(gp.first_order, s_p[li - 2 * PW], s_p[li - PW], s_p[li], s_p[li + PW],
-                              s_p[li + 2 * PW], s_p[li + 3 * PW], yp[o], yp[o + TX]);
+                parabola_run<NC, PW, TX>(gp.first_order, (fp ? s_p : s_vy) + li, (fp ? yp : yv) + o);
             }
         }
         __syncthreads();
