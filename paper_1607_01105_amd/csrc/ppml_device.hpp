@@ -94,6 +94,12 @@ __device__ __forceinline__ double dabs(double x) { return __builtin_fabs(x); }
 __device__ __forceinline__ float dcopysign(float m, float s) { return __builtin_copysignf(m, s); }
 __device__ __forceinline__ double dcopysign(double m, double s) { return __builtin_copysign(m, s); }
 __device__ __forceinline__ float dmin(float a, float b) { return __builtin_fminf(a, b); }
+// median of a, b and 0
+__device__ __forceinline__ float med0(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
+__device__ __forceinline__ double med0(double a, double b)
+{
+    return __builtin_fmax(__builtin_fmin(a, b), __builtin_fmin(__builtin_fmax(a, b), 0.0));
+}
 __device__ __forceinline__ double dmin(double a, double b) { return __builtin_fmin(a, b); }
 
 // Reciprocal and reciprocal square root of a positive normal value for the
@@ -206,23 +212,6 @@ template <typename T> struct Parab {
 
 template <typename T> __device__ __forceinline__ Parab<T> monotonize(T c, T l, T r)
 {
-#ifndef PPML_EXACT
-    // The same rules in terms of the one-sided jumps dl = c - l, dr = r - c:
-    // with dl, dr of one sign (otherwise the cell is flattened),
-    // d * q6 > d^2 <=> (dl - 2 dr)(dl + dr) > 0 <=> |dl| > 2|dr|, where the new
-    // left edge 3c - 2r = c - 2 dr; d * q6 < -d^2 <=> |dr| > 2|dl|, new right
-    // edge c + 2 dl.  Equal to the rounding of the two forms (the limiter is
-    // continuous across every branch boundary).
-    const T dl = c - l, dr = r - c;
-    const bool flat = dl * dr <= T(0);
-    const T L = flat ? c : (dabs(dl) > K<T>::two * dabs(dr) ? c - K<T>::two * dr : l);
-    const T R = flat ? c : (dabs(dr) > K<T>::two * dabs(dl) ? c + K<T>::two * dl : r);
-    Parab<T> q;
-    q.L = L;
-    q.R = R;
-    q.Q6 = K<T>::six * (c - K<T>::half * (L + R));
-    return q;
-#endif
     if ((r - c) * (c - l) <= T(0)) {
         l = c;
         r = c;
@@ -242,29 +231,6 @@ template <typename T> __device__ __forceinline__ Parab<T> monotonize(T c, T l, T
     return p;
 }
 
-// Product build: of a cell's monotonised parabola the Lagrangian stage needs
-// only the two edge values and the cell value (the curvature coefficient is
-// 6 c - 3 (L + R)), and of the mean over the strip of width z h next to an
-// interface only the weights of the upwind cell's near edge, far edge and
-// value.  Expanding either strip mean (avg_left, avg_right below) with that
-// coefficient gives
-//   (1 - z)^2 near + z (z - 1) far + z (3 - 2 z) c,
-// weights that depend on z alone and serve every field of the interface.
-template <typename T> struct Edges {
-    T L, R, C;
-};
-template <typename T> __device__ __forceinline__ Edges<T> mono_edges(int first_order, T c, T l, T r)
-{
-    // the rules of monotonize, in terms of the one-sided jumps; the
-    // first-order scheme's constant state is the flattened profile (folded
-    // into the same selects, so that no branch splits the fields' loads)
-    const T dl = c - l, dr = r - c;
-    const bool flat = first_order != 0 || dl * dr <= T(0);
-    const T L = flat ? c : (dabs(dl) > K<T>::two * dabs(dr) ? c - K<T>::two * dr : l);
-    const T R = flat ? c : (dabs(dr) > K<T>::two * dabs(dl) ? c + K<T>::two * dl : r);
-    return Edges<T>{L, R, c};
-}
-
 // The first-order scheme's constant state (Sec. 2.1) in place of the
 // parabola p of a cell of value c.  Selected after the parabola is built, so
 // that the choice is a select rather than a branch between the fields.
@@ -275,16 +241,25 @@ template <typename T> __device__ __forceinline__ Parab<T> pick_profile(int first
 }
 
 // State profile of a cell: the monotonised parabola, or the constant cell
-// value in the first-order scheme.  The product build takes the constant
-// state as a flattened cell (L = R = c gives Q6 = 0 exactly), so that no
-// select follows the parabola.
+// value in the first-order scheme.
 template <typename T> __device__ __forceinline__ Parab<T> profile(int first_order, T c, T l, T r)
 {
 #ifdef PPML_EXACT
     return pick_profile(first_order, c, monotonize(c, l, r));
 #else
-    const Edges<T> e = mono_edges(first_order, c, l, r);
-    return Parab<T>{e.L, e.R, K<T>::six * (c - K<T>::half * (e.L + e.R))};
+    // The rules of monotonize in terms of the one-sided jumps dl = c - l,
+    // dr = r - c: with dl, dr of one sign (otherwise the cell is flattened),
+    // d * q6 > d^2 <=> (dl - 2 dr)(dl + dr) > 0 <=> |dl| > 2|dr|, where the new
+    // left edge 3c - 2r = c - 2 dr; d * q6 < -d^2 <=> |dr| > 2|dl|, new right
+    // edge c + 2 dl.  Equal to the rounding of the two forms (the limiter is
+    // continuous across every branch boundary).  The first-order constant
+    // state is the flattened cell (L = R = c gives Q6 = 0 exactly), folded
+    // into the flattening test so that no select follows the parabola.
+    const T dl = c - l, dr = r - c;
+    const bool flat = first_order != 0 || dl * dr <= T(0);
+    const T L = flat ? c : (dabs(dl) > K<T>::two * dabs(dr) ? c - K<T>::two * dr : l);
+    const T R = flat ? c : (dabs(dr) > K<T>::two * dabs(dl) ? c + K<T>::two * dl : r);
+    return Parab<T>{L, R, K<T>::six * (c - K<T>::half * (L + R))};
 #endif
 }
 
@@ -390,17 +365,41 @@ template <typename T> __device__ __forceinline__ T upwind_flux(T vh, T z, const 
     return vh * fs;
 }
 
-template <typename T> struct StripW {
-    T near, far, mid;
+// Product build, Lagrangian stage: a cell's monotonised profile as its value
+// and its one-sided jumps dl = c - L, dr = R - c.  In these terms the rules of
+// monotonize are: jumps of different sign, or a zero jump, flatten the cell;
+// otherwise a jump larger than twice the other is cut to twice the other.
+// The median of (d, 2 d_other, 0) applies all of them at once: it is 0 when d
+// and d_other differ in sign, and otherwise whichever of d and 2 d_other is
+// nearer to 0.
+template <typename T> struct Jumps {
+    T dl, dr, c;
 };
-template <typename T> __device__ __forceinline__ StripW<T> strip_weights(T z)
+template <typename T> __device__ __forceinline__ Jumps<T> mono_jumps(T c, T l, T r)
 {
-    const T y = T(1) - z;
-    return StripW<T>{y * y, -(z * y), z * (K<T>::three - K<T>::two * z)};
+    const T dl = c - l, dr = r - c;
+    return Jumps<T>{med0(dl, dr + dr), med0(dr, dl + dl), c};
 }
-template <typename T> __device__ __forceinline__ T strip_mean(const StripW<T> &w, T near, T far, T c)
+// Weights of the upwind flux through a face, vs = v tau / h, z = |vs|.  With
+// the strip mean written as c plus the weighted edge offsets (the weights
+// (1 - z)^2, z (z - 1), z (3 - 2 z) sum to 1), the flux times tau / h is
+//   vs c + a dr + b dl,
+// a = z (1 - z)^2, b = z^2 (1 - z) when the upwind cell is on the left, and
+// the two swapped when it is on the right.  The first-order scheme's constant
+// state has a = b = 0.
+template <typename T> struct FaceW {
+    T vs, a, b;
+};
+template <typename T> __device__ __forceinline__ FaceW<T> face_weights(int first_order, bool left, T vs)
 {
-    return w.near * near + (w.far * far + w.mid * c);
+    const T z = first_order != 0 ? T(0) : dabs(vs);
+    const T zy = z * (T(1) - z);
+    const T p = zy * (T(1) - z), q = zy * z;
+    return FaceW<T>{vs, left ? p : q, left ? q : p};
+}
+template <typename T> __device__ __forceinline__ T face_flux(const FaceW<T> &w, const Jumps<T> &u)
+{
+    return w.vs * u.c + (w.a * u.dr + w.b * u.dl);
 }
 
 // Density-weighted interface velocity (Sec. 2.3).

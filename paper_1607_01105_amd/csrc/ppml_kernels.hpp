@@ -836,14 +836,14 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
     }
 
     // z pipeline registers (3-D), one set per field.  The profile of the
-    // previous cell: its parabola in the exact build, its edge values and
-    // value in the product build.
+    // previous cell: its parabola in the exact build, its value and
+    // monotonised one-sided jumps in the product build.
 #ifdef PPML_EXACT
     using Prof = Parab<T>;
     const Prof prof_one{T(1), T(1), T(0)};
 #else
-    using Prof = Edges<T>;
-    const Prof prof_one{T(1), T(1), T(1)};
+    using Prof = Jumps<T>;
+    const Prof prof_one{T(0), T(0), T(1)};
 #endif
     T q0[NF], q1[NF], q2[NF], dmq[NF], qI[NF], Fzp[NF];
     Prof pprev[NF];
@@ -1048,7 +1048,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
 #ifdef PPML_EXACT
                 pnew[f] = profile(gp.first_order, q0[f], qI[f], qInew);
 #else
-                pnew[f] = mono_edges(gp.first_order, q0[f], qI[f], qInew);
+                pnew[f] = mono_jumps(q0[f], qI[f], qInew);
 #endif
                 dmq[f] = dnew;
                 qI[f] = qInew;
@@ -1078,13 +1078,12 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                 }
 #else
                 // fluxes times tau / h_z: the update subtracts their differences
-                const T vs = vh * tohz;
-                const StripW<T> w = strip_weights(dabs(vs));
                 const bool up = vh >= T(0);
+                const FaceW<T> w = face_weights(gp.first_order, up, vh * tohz);
 #pragma unroll
                 for (int f = 0; f < NF; f++) {
                     const Prof &a = pprev[f], &b = pnew[f];
-                    const T F = vs * strip_mean(w, up ? a.R : b.L, up ? a.L : b.R, up ? a.C : b.C);
+                    const T F = face_flux(w, Prof{up ? a.dl : b.dl, up ? a.dr : b.dr, up ? a.c : b.c});
                     DFz[f] = F - Fzp[f];
                     Fzp[f] = F;
                 }
@@ -1333,13 +1332,11 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                         Fr[r][g] = vh * fs;
                     }
 #else
-                    const T vs = vh * tohx;  // fluxes times tau / h_x
-                    const StripW<T> w = strip_weights(dabs(vs));
+                    const FaceW<T> w = face_weights(gp.first_order, left, vh * tohx);  // fluxes times tau / h_x
 #pragma unroll
                     for (int g = 0; g < G; g++) {
                         if (f0 + g >= NF) break;
-                        const Edges<T> e = mono_edges(gp.first_order, sf[g][lq], s_qx[g][lf], s_qx[g][lf + 1]);
-                        Fr[r][g] = vs * strip_mean(w, left ? e.R : e.L, left ? e.L : e.R, e.C);
+                        Fr[r][g] = face_flux(w, mono_jumps(sf[g][lq], s_qx[g][lf], s_qx[g][lf + 1]));
                     }
 #endif
                 } else if (NDIM >= 2 && j < NXI + NYI) {
@@ -1378,13 +1375,11 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                         Fr[r][g] = vh * fs;
                     }
 #else
-                    const T vs = vh * tohy;  // fluxes times tau / h_y
-                    const StripW<T> w = strip_weights(dabs(vs));
+                    const FaceW<T> w = face_weights(gp.first_order, left, vh * tohy);  // fluxes times tau / h_y
 #pragma unroll
                     for (int g = 0; g < G; g++) {
                         if (f0 + g >= NF) break;
-                        const Edges<T> e = mono_edges(gp.first_order, sf[g][lq], s_qy[g][lf], s_qy[g][lf + 1]);
-                        Fr[r][g] = vs * strip_mean(w, left ? e.R : e.L, left ? e.L : e.R, e.C);
+                        Fr[r][g] = face_flux(w, mono_jumps(sf[g][lq], s_qy[g][lf], s_qy[g][lf + 1]));
                     }
 #endif
                 }
