@@ -240,37 +240,47 @@ template <typename T> __device__ __forceinline__ Parab<T> pick_profile(int first
     return Parab<T>{fo ? c : p.L, fo ? c : p.R, fo ? T(0) : p.Q6};
 }
 
+// Product build: a cell's monotonised profile as its value and its one-sided
+// jumps dl = c - L, dr = R - c.  In these terms the rules of monotonize are:
+// jumps of different sign, or a zero jump, flatten the cell; otherwise a jump
+// larger than twice the other is cut to twice the other.  The median of
+// (d, 2 d_other, 0) applies all of them at once: it is 0 when d and d_other
+// differ in sign, and otherwise whichever of d and 2 d_other is nearer to 0.
+template <typename T> struct Jumps {
+    T dl, dr, c;
+};
+template <typename T> __device__ __forceinline__ Jumps<T> mono_jumps(T c, T l, T r)
+{
+    const T dl = c - l, dr = r - c;
+    return Jumps<T>{med0(dl, dr + dr), med0(dr, dl + dl), c};
+}
+
 // State profile of a cell: the monotonised parabola, or the constant cell
-// value in the first-order scheme.
-template <typename T> __device__ __forceinline__ Parab<T> profile(int first_order, T c, T l, T r)
+// value in the first-order scheme, in the exact build; the value and the
+// monotonised jumps in the product build, whose strip means apply the
+// first-order scheme through their weights.
+#ifdef PPML_EXACT
+template <typename T> using Profile = Parab<T>;
+#else
+template <typename T> using Profile = Jumps<T>;
+#endif
+template <typename T> __device__ __forceinline__ Profile<T> profile(int first_order, T c, T l, T r)
 {
 #ifdef PPML_EXACT
     return pick_profile(first_order, c, monotonize(c, l, r));
 #else
-    // The rules of monotonize in terms of the one-sided jumps dl = c - l,
-    // dr = r - c: with dl, dr of one sign (otherwise the cell is flattened),
-    // d * q6 > d^2 <=> (dl - 2 dr)(dl + dr) > 0 <=> |dl| > 2|dr|, where the new
-    // left edge 3c - 2r = c - 2 dr; d * q6 < -d^2 <=> |dr| > 2|dl|, new right
-    // edge c + 2 dl.  Equal to the rounding of the two forms (the limiter is
-    // continuous across every branch boundary).  The first-order constant
-    // state is the flattened cell (L = R = c gives Q6 = 0 exactly), folded
-    // into the flattening test so that no select follows the parabola.
-    const T dl = c - l, dr = r - c;
-    const bool flat = first_order != 0 || dl * dr <= T(0);
-    const T L = flat ? c : (dabs(dl) > K<T>::two * dabs(dr) ? c - K<T>::two * dr : l);
-    const T R = flat ? c : (dabs(dr) > K<T>::two * dabs(dl) ? c + K<T>::two * dl : r);
-    return Parab<T>{L, R, K<T>::six * (c - K<T>::half * (L + R))};
+    (void)first_order;
+    return mono_jumps(c, l, r);
 #endif
 }
 
-// Parabolas of NC consecutive cells of a line, q[0], q[S], ..., q[(NC - 1) S]
+// Profiles of NC consecutive cells of a line, q[0], q[S], ..., q[(NC - 1) S]
 // (values q[-2 S] .. q[(NC + 1) S]), written to out[0], out[OS], ...: each
 // slope and interface value is built once and serves the cells on both of
-// its sides, and each parabola comes from its cell's three slopes and two
-// interface values by the same operations as on its own.  Constant states in
-// the first-order scheme.
+// its sides, and each profile comes from its cell's three slopes and two
+// interface values by the same operations as on its own.
 template <int NC, int S, int OS, typename T>
-__device__ __forceinline__ void parabola_run(int first_order, const T *q, Parab<T> *out)
+__device__ __forceinline__ void parabola_run(int first_order, const T *q, Profile<T> *out)
 {
     T v[NC + 4];  // cells -2 .. NC + 1
 #pragma unroll
@@ -317,9 +327,9 @@ template <typename T> struct VP {
 };
 
 template <typename T>
-__device__ __forceinline__ VP<T> riemann(T sa, T sb, T r32a, T r32b, T psa, T psb, const Parab<T> &va,
-                                         const Parab<T> &vb, const Parab<T> &pa, const Parab<T> &pb, T gamma,
-                                         T tau, T h, T tau_over_h)
+__device__ __forceinline__ VP<T> riemann(int first_order, T sa, T sb, T r32a, T r32b, T psa, T psb,
+                                         const Profile<T> &va, const Profile<T> &vb, const Profile<T> &pa,
+                                         const Profile<T> &pb, T gamma, T tau, T h, T tau_over_h)
 {
     T A = r32a + r32b;
     T B = sa + sb;
@@ -343,10 +353,25 @@ __device__ __forceinline__ VP<T> riemann(T sa, T sb, T r32a, T r32b, T psa, T ps
     const T iZ = B * iA * rl;
     T z = lam * tau_over_h;
 #endif
+#ifdef PPML_EXACT
+    (void)first_order;
     T vm = avg_left(va.L, va.R, va.Q6, z);
     T vp = avg_right(vb.L, vb.R, vb.Q6, z);
     T pm = avg_left(pa.L, pa.R, pa.Q6, z);
     T pp = avg_right(pb.L, pb.R, pb.Q6, z);
+#else
+    // the strip means in terms of the monotonised jumps (L = c - dl,
+    // R = c + dr, Q6 = 3 (dl - dr)): next to the right edge of the left cell
+    // c + (1 - z)^2 dr + z (1 - z) dl, next to the left edge of the right
+    // cell c - (1 - z)^2 dl - z (1 - z) dr; both weights vanish for the
+    // first-order constant states
+    const T y = T(1) - z;
+    const T wn = first_order != 0 ? T(0) : y * y, wf = first_order != 0 ? T(0) : z * y;
+    T vm = va.c + (wn * va.dr + wf * va.dl);
+    T vp = vb.c - (wn * vb.dl + wf * vb.dr);
+    T pm = pa.c + (wn * pa.dr + wf * pa.dl);
+    T pp = pb.c - (wn * pb.dl + wf * pb.dr);
+#endif
     VP<T> o;
 #ifdef PPML_EXACT
     o.V = K<T>::half * (vm + vp) + (pm - pp) / (K<T>::two * Z);
@@ -365,21 +390,6 @@ template <typename T> __device__ __forceinline__ T upwind_flux(T vh, T z, const 
     return vh * fs;
 }
 
-// Product build, Lagrangian stage: a cell's monotonised profile as its value
-// and its one-sided jumps dl = c - L, dr = R - c.  In these terms the rules of
-// monotonize are: jumps of different sign, or a zero jump, flatten the cell;
-// otherwise a jump larger than twice the other is cut to twice the other.
-// The median of (d, 2 d_other, 0) applies all of them at once: it is 0 when d
-// and d_other differ in sign, and otherwise whichever of d and 2 d_other is
-// nearer to 0.
-template <typename T> struct Jumps {
-    T dl, dr, c;
-};
-template <typename T> __device__ __forceinline__ Jumps<T> mono_jumps(T c, T l, T r)
-{
-    const T dl = c - l, dr = r - c;
-    return Jumps<T>{med0(dl, dr + dr), med0(dr, dl + dl), c};
-}
 // Weights of the upwind flux through a face, vs = v tau / h, z = |vs|.  With
 // the strip mean written as c plus the weighted edge offsets (the weights
 // (1 - z)^2, z (z - 1), z (3 - 2 z) sum to 1), the flux times tau / h is

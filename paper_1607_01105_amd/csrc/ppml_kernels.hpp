@@ -290,7 +290,7 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
     constexpr int NVY = NDIM >= 2 ? PS : 1;
     constexpr size_t B_TILE = ((size_t)(2 * PS + NVY) * sizeof(T) + 15) & ~(size_t)15;
     constexpr size_t B_IFACE = (size_t)(NXI + NYI) * sizeof(VP<T>);
-    constexpr size_t B_REST = (size_t)3 * PS * sizeof(T) + (size_t)2 * (NXP + NYP) * sizeof(Parab<T>);
+    constexpr size_t B_REST = (size_t)3 * PS * sizeof(T) + (size_t)2 * (NXP + NYP) * sizeof(Profile<T>);
     constexpr size_t GROUPS3 = NT >= 64 ? (size_t)12 / (NT / 64) : 12;  // groups per CU for 3 waves/SIMD
     constexpr size_t B_SEP = (B_TILE + B_IFACE + B_REST + 2047) & ~(size_t)2047;
     constexpr size_t B_OVL = ((B_TILE > B_IFACE ? B_TILE : B_IFACE) + B_REST + 2047) & ~(size_t)2047;
@@ -309,8 +309,8 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
     VP<T> *const xi = reinterpret_cast<VP<T> *>(s_union + (OVERLAY ? 0 : B_TILE));
     VP<T> *const yi = xi + NXI;
     __shared__ T s_s[PS], s_r32[PS], s_ps[PS];
-    __shared__ Parab<T> xv[NXP], xp[NXP];
-    __shared__ Parab<T> yv[NYP], yp[NYP];
+    __shared__ Profile<T> xv[NXP], xp[NXP];
+    __shared__ Profile<T> yv[NYP], yp[NYP];
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
@@ -399,7 +399,11 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
     T qv0 = 1, qv1 = 1, qv2 = 1, qp0 = 1, qp1 = 1, qp2 = 1;  // q_{m-2}, q_{m-1}, q_m
     T dmv = 0, dmp = 0;                                      // slope at m-2
     T qIv = 1, qIp = 1;                                      // interface value (m-3)+1/2
-    Parab<T> pv_prev = {1, 1, 0}, pp_prev = {1, 1, 0};       // parabola of cell m-3
+#ifdef PPML_EXACT
+    Profile<T> pv_prev = {1, 1, 0}, pp_prev = {1, 1, 0};     // profile of cell m-3
+#else
+    Profile<T> pv_prev = {0, 0, 1}, pp_prev = {0, 0, 1};
+#endif
     T sr0 = 1, sr1 = 1, sr2 = 1, sr3 = 1;                    // sqrt(rho) at m-3..m
     T rr0 = 1, rr1 = 1, rr2 = 1, rr3 = 1;                    // rho^{3/2}
     T pr0 = 1, pr1 = 1, pr2 = 1, pr3 = 1;                    // p sqrt(rho)
@@ -479,11 +483,11 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
             const T dp_new = limited_slope(qp0, qp1, qp2);
             const T qIv_new = interface_value(qv0, qv1, dmv, dv_new);
             const T qIp_new = interface_value(qp0, qp1, dmp, dp_new);
-            const Parab<T> pv_new = profile(gp.first_order, qv0, qIv, qIv_new);
-            const Parab<T> pp_new = profile(gp.first_order, qp0, qIp, qIp_new);
+            const Profile<T> pv_new = profile(gp.first_order, qv0, qIv, qIv_new);
+            const Profile<T> pp_new = profile(gp.first_order, qp0, qIp, qIp_new);
             dmv = dv_new; dmp = dp_new; qIv = qIv_new; qIp = qIp_new;
             // interface between planes m-3 and m-2
-            const VP<T> vpz = riemann(sr0, sr1, rr0, rr1, pr0, pr1, pv_prev, pv_new, pp_prev, pp_new, gam, tau, hz,
+            const VP<T> vpz = riemann(gp.first_order, sr0, sr1, rr0, rr1, pr0, pr1, pv_prev, pv_new, pp_prev, pp_new, gam, tau, hz,
                                       tohz);
             DPz = PPML_DIV(vpz.P - Pprev, hz, ihz);
             DPVz = PPML_DIV(vpz.P * vpz.V - Pprev * Vprev, hz, ihz);
@@ -605,7 +609,7 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
             const int ix = j % (TX + 1), cy = j / (TX + 1);
             const int la = (cy + HY) * PW + ix - 1 + HX, lb = la + 1;
             const int pa = cy * (TX + 2) + ix, pb = pa + 1;
-            xi[j] = riemann(s_s[la], s_s[lb], s_r32[la], s_r32[lb], s_ps[la], s_ps[lb], xv[pa], xv[pb], xp[pa], xp[pb],
+            xi[j] = riemann(gp.first_order, s_s[la], s_s[lb], s_r32[la], s_r32[lb], s_ps[la], s_ps[lb], xv[pa], xv[pb], xp[pa], xp[pb],
                             gam, tau, hx, tohx);
         }
         if constexpr (NDIM >= 2) {
@@ -615,7 +619,7 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
                 const int cx = j % TX, iy = j / TX;
                 const int la = (iy - 1 + HY) * PW + cx + HX, lb = la + PW;
                 const int pa = iy * TX + cx, pb = pa + TX;
-                yi[j] = riemann(s_s[la], s_s[lb], s_r32[la], s_r32[lb], s_ps[la], s_ps[lb], yv[pa], yv[pb], yp[pa],
+                yi[j] = riemann(gp.first_order, s_s[la], s_s[lb], s_r32[la], s_r32[lb], s_ps[la], s_ps[lb], yv[pa], yv[pb], yp[pa],
                                 yp[pb], gam, tau, hy, tohy);
             }
         }
@@ -838,11 +842,10 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
     // z pipeline registers (3-D), one set per field.  The profile of the
     // previous cell: its parabola in the exact build, its value and
     // monotonised one-sided jumps in the product build.
+    using Prof = Profile<T>;
 #ifdef PPML_EXACT
-    using Prof = Parab<T>;
     const Prof prof_one{T(1), T(1), T(0)};
 #else
-    using Prof = Jumps<T>;
     const Prof prof_one{T(0), T(0), T(1)};
 #endif
     T q0[NF], q1[NF], q2[NF], dmq[NF], qI[NF], Fzp[NF];
@@ -1045,11 +1048,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                 q2[f] = v;
                 const T dnew = limited_slope(q0[f], q1[f], q2[f]);
                 const T qInew = interface_value(q0[f], q1[f], dmq[f], dnew);
-#ifdef PPML_EXACT
                 pnew[f] = profile(gp.first_order, q0[f], qI[f], qInew);
-#else
-                pnew[f] = mono_jumps(q0[f], qI[f], qInew);
-#endif
                 dmq[f] = dnew;
                 qI[f] = qInew;
             }
