@@ -84,7 +84,7 @@ template <typename T> struct K {
     static constexpr T three = T(3);
     static constexpr T six = T(6);
     static constexpr T inv3 = T(1) / T(3);
-    static constexpr T inv6 = T(1) / T(6);
+    static constexpr T inv12 = T(1) / T(12);
 };
 
 __device__ __forceinline__ float dsqrt(float x) { return __builtin_sqrtf(x); }
@@ -183,23 +183,35 @@ __device__ __forceinline__ unsigned inflow_code_xy(const GridParams &gp, int i, 
     return fy >= 0 ? (unsigned)(fy + 1) : (fx >= 0 ? (unsigned)(fx + 1) : 0u);
 }
 
-// Appendix step 1: limited slope delta_m q of the middle value.
+// Appendix step 1: limited slope delta_m q of the middle value.  The product
+// build returns 2 delta_m q, the form interface_value takes there.
 template <typename T> __device__ __forceinline__ T limited_slope(T qm, T q0, T qp)
 {
+#ifdef PPML_EXACT
     T dq = K<T>::half * (qp - qm);
     T dplus = qp - q0;
     T dminus = q0 - qm;
     T m = dmin(dabs(dq), dmin(K<T>::two * dabs(dplus), K<T>::two * dabs(dminus)));
     return (dplus * dminus > T(0)) ? dcopysign(m, dq) : T(0);
+#else
+    // With d+ = qp - q0, d- = q0 - qm: med(d+, d-, 0) is 0 unless d+ d- > 0,
+    // and then the one of the two nearer 0, so 4 med(d+, d-, 0) is the limit
+    // 2 min(|d+|, |d-|), doubled and signed; the median of it, 2 dq = qp - qm
+    // and 0 is twice the limited slope.  Every scaling is by a power of two,
+    // so the result is exactly twice the paper's slope (barring underflow of
+    // the product d+ d-).
+    return med0(qp - qm, T(4) * med0(qp - q0, q0 - qm));
+#endif
 }
 
-// Appendix step 1: fourth-order interface value between q0 and q1.
+// Appendix step 1: fourth-order interface value between q0 and q1 from the
+// limited slopes of the two cells (product build: twice the slopes).
 template <typename T> __device__ __forceinline__ T interface_value(T q0, T q1, T dm0, T dm1)
 {
 #ifdef PPML_EXACT
     return K<T>::half * (q0 + q1) - (dm1 - dm0) / K<T>::six;
 #else
-    return K<T>::half * (q0 + q1) - (dm1 - dm0) * K<T>::inv6;
+    return K<T>::half * (q0 + q1) - (dm1 - dm0) * K<T>::inv12;
 #endif
 }
 
