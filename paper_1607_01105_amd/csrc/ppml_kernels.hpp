@@ -51,11 +51,12 @@ template <int NT, int NA, int NB> struct JobMap {
 };
 
 // The value of the previous lane of the 16-lane DPP row (row_shr:1); lane
-// 0 of each row gets its own value.  Every lane of the row must be active.
+// 0 of each row, which has no previous lane, gets 0.  Every lane of the row
+// must be active.
 __device__ __forceinline__ float dpp_prev16(float v)
 {
     const int i = __builtin_bit_cast(int, v);
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, 0x111, 0xF, 0xF, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(i, 0x111, 0xF, 0xF, true));
 }
 
 // The wave's index in its work group, as a wave-uniform (scalar) value.
@@ -874,7 +875,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
         for (int r = 0; r < RC; r++) {
             if (ccode[r] < 0) continue;
             const int c = kk * plane + ccode[r];
-            const int wbase = r * NT + (tid & ~63);
+            const int wbase = r * NT + wv * 64;  // the wave's first slot (scalar)
 #pragma unroll
             for (int f = 0; f < NF; f++)
                 __builtin_amdgcn_global_load_lds((const void *)(Wf[f] + c),
