@@ -1,4 +1,4 @@
-// ppml_kernels.hpp -- HIP kernels of the PPML operator-splitting update on
+// ppml_kernels.hip -- HIP kernels of the PPML operator-splitting update on
 // gfx950.  One step is two fused kernels:
 //
 //   k_euler : Eulerian stage (Sec. 2.1-2.2): reconstruct v_d and p along
