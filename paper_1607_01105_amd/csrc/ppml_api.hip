@@ -513,9 +513,9 @@ template <typename T> void stage_slots(int device, int tile, int xf, long long &
     slots_l = (long long)cus * (bl > 0 ? bl : 2);
 }
 
-// Work-group tiling of a grid for tile shape v: x/y tiles, and the z chunk
-// of the batched launches (small enough that a 3-D grid alone gives the
-// launch a few thousand work groups).
+// Work-group tiling of a grid for tile shape v: x/y tiles, and a z chunk
+// small enough that a 3-D grid alone gives the launch a few thousand work
+// groups (batches then fit the chunks of their 3-D grids together).
 void set_tiling(GridParams &gp, int ndim, int v)
 {
     const int tx = TILE_X[ndim][v], ty = TILE_Y[ndim][v];
@@ -537,6 +537,39 @@ void set_chunks(GridParams &gp, int chunks)
     const int nz = gp.n[2];
     gp.cz = (nz + chunks - 1) / chunks;
     gp.tiles[2] = (nz + gp.cz - 1) / gp.cz;
+}
+
+// Z chunks shared by the 3-D grids of a batch: every work group of the launch
+// streams at most cz planes after its start-up (`warm`, in plane units).  With
+// the groups' work spread over the resident slots, the launch takes about
+// max(sum of the groups' lengths / slots, the longest group); cz minimises
+// that over all the batch's grids at once, where chunks chosen per grid as if
+// it ran alone cut every grid into short chunks whose start-up dominates.
+int batch_cz3(const std::vector<GridParams *> &gps, long long slots, double warm)
+{
+    int nzmax = 1;
+    for (const GridParams *gp : gps) nzmax = gp->n[2] > nzmax ? gp->n[2] : nzmax;
+    if (slots < 1) slots = 1;
+    int best = nzmax;
+    double best_t = 1e300;
+    for (int c = 1; c <= nzmax; c++) {
+        const int cz = (nzmax + c - 1) / c;
+        if ((long long)(c - 1) * cz >= nzmax) continue;  // same cz as a smaller count
+        double work = 0.0, longest = 0.0;
+        for (const GridParams *gp : gps) {
+            const int nz = gp->n[2];
+            const int ch = (nz + cz - 1) / cz;
+            const int czg = (nz + ch - 1) / ch;
+            work += (double)gp->tiles[0] * gp->tiles[1] * ch * (czg + warm);
+            longest = czg + warm > longest ? czg + warm : longest;
+        }
+        const double t = work / (double)slots > longest ? work / (double)slots : longest;
+        if (t < best_t * (1.0 - 1e-9)) {
+            best_t = t;
+            best = cz;
+        }
+    }
+    return best;
 }
 
 }  // namespace
@@ -1251,16 +1284,32 @@ int batch_rebuild(ppml_batch *b)
             BatchEntry &e = b->h_ents[n];
             e.gp = g->gp;
             set_tiling(e.gp, nd, b->tile[nd]);
+            b->entry_slot.push_back(s);
+            n++;
+        }
+        b->gn[nd] = n - b->goff[nd];
+        if (nd == 3 && b->gn[3] > 0) {
+            // one chunk length for all 3-D grids, fitted to the Lagrangian
+            // kernel's resident work groups (its start-up: 6 z-only planes,
+            // about 3 full ones)
+            std::vector<GridParams *> gps;
+            for (int i = b->goff[3]; i < n; i++) gps.push_back(&b->h_ents[i].gp);
+            long long se, sl;
+            if (b->prec == PPML_FP64) stage_slots<double>(b->device, b->tile[3], 0, se, sl);
+            else stage_slots<float>(b->device, b->tile[3], 0, se, sl);
+            const int cz = batch_cz3(gps, sl, 3.0);
+            for (GridParams *gp : gps) set_chunks(*gp, (gp->n[2] + cz - 1) / cz);
+        }
+        for (int i = b->goff[nd]; i < n; i++) {
+            BatchEntry &e = b->h_ents[i];
+            const ppml_grid *g = b->slots[b->entry_slot[i]];
             e.state = g->state;
             e.half = g->half;
             e.ctrl = g->ctrl;
             e.tile0 = tiles;
             e.pad = 0;
             tiles += e.gp.tiles[0] * e.gp.tiles[1] * e.gp.tiles[2];
-            b->entry_slot.push_back(s);
-            n++;
         }
-        b->gn[nd] = n - b->goff[nd];
         b->gtiles[nd] = tiles;
     }
     if (n > 0) {
