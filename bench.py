@@ -410,7 +410,8 @@ def run_gravity(n=256, steps=50):
                        f"p = 0.05, outflow, CFL 0.3, {steps} steps", "cells": cells, "steps": steps}
     rho = {}
     for prec in ("fp32", "fp64"):
-        tile = autotune.tune_grid(prob, prec, steps=3, warmup=1)["tile"]
+        # trials long enough to tell tile shapes within 10% of each other apart
+        tile = autotune.tune_grid(prob, prec, steps=8, warmup=2)["tile"]
         g = Grid.from_problem(prob, prec=prec, tile=tile)
         g.step(2)
         g.sync()
