@@ -4,13 +4,16 @@ Requests of a served trace arrive on a Poisson clock.  Each scheduler round
 
 1. admits the grids prepared during the previous round into the batch;
 2. enqueues the advance of every admitted grid by min(its remaining steps,
-   round_steps) in one batched launch sequence (every grid keeps its own CFL
-   time step);
+   round_steps) in one batched launch sequence, replayed as a captured HIP
+   graph (captured again when the batch's grids change; every grid keeps its
+   own CFL time step);
 3. while the GPU runs that round, prepares arrived requests, oldest first,
    while the memory budget (state + scratch of the admitted and prepared
    grids) and the batch capacity allow: the request's initial state is
    copied to new device buffers on a second stream, so the copies and the
-   state conversion overlap the batch's kernels;
+   state conversion overlap the batch's kernels; a request whose initial
+   data are still being generated joins a later round unless nothing else
+   could run, so the GPU starts on what is ready;
 4. waits for the round and retires grids whose steps are done; their final
    states are copied to the host while the next round runs (before that
    round's admissions are prepared), the completion latency (arrival -> final
@@ -57,7 +60,7 @@ class Server:
     """Continuous-batching server over the batch API of the HIP library."""
 
     def __init__(self, budget_bytes: int = 4 << 30, capacity: int = 256, prec: str = "fp32", round_steps: int = 50,
-                 graph: bool = False, device: str = "cuda", prep_workers: int = 8, lookahead: int = 16,
+                 graph: bool = True, device: str = "cuda", prep_workers: int = 8, lookahead: int = 16,
                  keep_results: bool = False, batch=None, tiles: dict | None = None):
         from .ppml import Batch
 
@@ -117,15 +120,21 @@ class Server:
 
         def prepare():
             # FIFO while budget and capacity allow: state set on the side
-            # stream (the call returns once the state is on the device)
+            # stream (the call returns once the state is on the device).  A
+            # request whose fields are still being generated waits for a later
+            # round unless nothing else could run, so the GPU starts on what
+            # is ready instead of idling until the budget is filled.
             nonlocal in_use
             while waiting and len(active) + len(prepared) < self.capacity:
                 r = waiting[0]
                 need = self._grid_bytes(r)
                 if in_use + need > self.budget:
                     break
+                fut = futures.get(r.rid)
+                if fut is not None and not fut.done() and (prepared or active):
+                    break
                 t_req = clock()
-                fut = futures.pop(r.rid, None)
+                futures.pop(r.rid, None)
                 prob = fut.result() if fut is not None else r.problem()
                 data_wait = max(0.0, clock() - max(t_req, r.arrival * time_scale))
                 g = self.batch.new_grid(prob, prec=self.prec, stream=side)
