@@ -94,6 +94,50 @@ def test_scheduler_logic_cpu():
         assert np.array_equal(srv.results[r.rid], o.get("rho")), r.rid
 
 
+def test_round_does_not_wait_for_data_still_being_generated_cpu():
+    """A request whose initial data are still being generated joins a later
+    round: the requests that are ready are stepped meanwhile, and admission
+    stays first come, first served."""
+    import dataclasses
+    import threading
+
+    from paper_1607_01105_amd import ppml
+    from paper_1607_01105_amd.serve import Server
+
+    release = threading.Event()
+
+    @dataclasses.dataclass
+    class SlowRequest(W.Request):
+        def problem(self):
+            release.wait(timeout=60)
+            return super().problem()
+
+    fast, second = _small_trace(n=2, seed=7)
+    slow = SlowRequest(**dataclasses.asdict(second))
+    lib = ppml.load()
+    fake = _FakeBatch(capacity=4, budget=1 << 30, lib=lib)
+    resident = []
+    step = fake.step
+
+    def step_and_release(nsteps, steps, graph=False):
+        resident.append(len(fake.grids))
+        step(nsteps, steps, graph)
+        release.set()  # the slow request's data arrive once a round has run
+
+    fake.step = step_and_release
+    srv = Server(budget_bytes=1 << 30, capacity=4, round_steps=2, keep_results=True, batch=fake, prep_workers=2)
+    st = srv.run([fast, slow], time_scale=0.0)
+    assert st["requests"] == 2
+    assert resident[0] == 1  # the first round ran the ready request alone
+    assert fake.order == [fast.problem().name, slow.problem().name]
+    for r in (fast, slow):
+        o = oracle.Oracle(r.ndim, (r.n,) * r.ndim, (0.0,) * r.ndim, (1.0,) * r.ndim, 5.0 / 3.0, 0.3, bc="periodic")
+        p = r.problem()
+        o.set_primitive(p.rho, p.vx, p.vy, p.vz, p.p)
+        o.run(r.steps)
+        assert np.array_equal(srv.results[r.rid], o.get("rho")), r.rid
+
+
 @pytest.mark.gpu
 def test_served_results_equal_alone_gpu():
     """GPU: requests served in a changing mix (budget forces queueing, rounds
