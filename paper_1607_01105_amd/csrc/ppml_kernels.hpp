@@ -919,7 +919,10 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
     };
     (void)fix_cross;
 
-    for (int m = m_beg; m < m_end; ++m) {
+    // One plane's work: ppv holds the profiles of the previous cell of the
+    // column, pnw receives the new ones.
+    Prof pB[NF];
+    auto plane_step = [&](const int m, Prof(&ppv)[NF], Prof(&pnw)[NF]) __attribute__((always_inline)) {
         const int k = NDIM == 3 ? m - 3 : 0;
         T DFz[NF];
 #pragma unroll
@@ -1039,7 +1042,6 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
 
         if constexpr (NDIM == 3) {
             // own column, plane m, every field: z parabola of cell m-2
-            Prof pnew[NF];
 #pragma unroll
             for (int f = 0; f < NF; f++) {
                 T v = ov[f];
@@ -1049,7 +1051,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                 q2[f] = v;
                 const T dnew = limited_slope(q0[f], q1[f], q2[f]);
                 const T qInew = interface_value(q0[f], q1[f], dmq[f], dnew);
-                pnew[f] = profile(gp.first_order, q0[f], qI[f], qInew);
+                pnw[f] = profile(gp.first_order, q0[f], qI[f], qInew);
                 dmq[f] = dnew;
                 qI[f] = qInew;
             }
@@ -1072,7 +1074,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                 const T z = dabs(vh) * tau / hz;
 #pragma unroll
                 for (int f = 0; f < NF; f++) {
-                    const T F = upwind_flux(vh, z, pprev[f], pnew[f]);
+                    const T F = upwind_flux(vh, z, ppv[f], pnw[f]);
                     DFz[f] = (F - Fzp[f]) / hz;
                     Fzp[f] = F;
                 }
@@ -1082,7 +1084,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
                 const FaceW<T> w = face_weights(gp.first_order, up, vh * tohz);
 #pragma unroll
                 for (int f = 0; f < NF; f++) {
-                    const Prof &a = pprev[f], &b = pnew[f];
+                    const Prof &a = ppv[f], &b = pnw[f];
                     const T F = face_flux(w, Prof{up ? a.dl : b.dl, up ? a.dr : b.dr, up ? a.c : b.c});
                     DFz[f] = F - Fzp[f];
                     Fzp[f] = F;
@@ -1090,9 +1092,7 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
 #endif
                 vtz_prev = vt;
             }
-#pragma unroll
-            for (int f = 0; f < NF; f++) pprev[f] = pnew[f];
-            if (k < z0) continue;  // warm-up: uniform over the block
+            if (k < z0) return;  // warm-up: uniform over the block
         } else {
             __syncthreads();
         }
@@ -1474,6 +1474,22 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
             if (bad) atomicOr(&ctrl->err, 1);
             vmax = vmax > v ? vmax : v;
             cmax = cmax > cs ? cmax : cs;
+        }
+    };
+    // FP32 3-D: two planes per trip with the profile sets exchanged, so that
+    // no profile is copied from one plane to the next; an odd count of
+    // planes starts one plane lower, whose state only reaches warm-up planes.
+    // Otherwise one plane per trip and a copy.
+    if constexpr (NDIM == 3 && sizeof(T) == 4) {
+        for (int m = ((m_end - m_beg) & 1) ? m_beg - 1 : m_beg; m < m_end; m += 2) {
+            plane_step(m, pprev, pB);
+            plane_step(m + 1, pB, pprev);
+        }
+    } else {
+        for (int m = m_beg; m < m_end; ++m) {
+            plane_step(m, pprev, pB);
+#pragma unroll
+            for (int f = 0; f < NF; f++) pprev[f] = pB[f];
         }
     }
     publish_max(ctrl, sl ^ 1, (double)vmax, (double)cmax);
