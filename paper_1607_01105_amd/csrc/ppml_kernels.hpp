@@ -919,577 +919,28 @@ __device__ __forceinline__ void lagr_body(const T *__restrict__ Wst, T *__restri
     };
     (void)fix_cross;
 
-    // One plane's work: ppv holds the profiles of the previous cell of the
-    // column, pnw receives the new ones.
-    Prof pB[NF];
-    auto plane_step = [&](const int m, Prof(&ppv)[NF], Prof(&pnw)[NF]) __attribute__((always_inline)) {
-        const int k = NDIM == 3 ? m - 3 : 0;
-        T DFz[NF];
-#pragma unroll
-        for (int f = 0; f < NF; f++) DFz[f] = T(0);
-
-        // own column, plane m, every field (3-D), loaded together with the
-        // velocity tile below so that the plane costs one memory latency
-        T ov[NF];
-        int fzo = 0;
-        if constexpr (NDIM == 3) {
-            const int mz = map_index(m, nz, gp.bc_lo[2], gp.bc_hi[2], fzo);
-            const int c = mz * plane + own_off;
-#pragma unroll
-            for (int f = 0; f < NF; f++) ov[f] = Wf[f][c];
-            if (gp.any_inflow) {  // plane m is a ghost of an inflow z face
-                const int fzi = inflow_face(m, nz, gp.bc_lo[2], gp.bc_hi[2], 2);
-                if (fzi >= 0) {
-#pragma unroll
-                    for (int f = 0; f < NF; f++) ov[f] = inflow_value<T>(ctrl, fzi, inflow_component<NDIM>(f));
-                    fzo = 0;
-                }
-            }
-        }
-
-        // velocity plane needed by this iteration (3-D: plane m-2; else plane 0)
-        const int vpl = NDIM == 3 ? m - 2 : 0;
-        const int slot = NDIM == 3 ? ((vpl % 3) + 3) % 3 : 0;
-        const int zslot = NDIM == 3 ? (vpl & 1) : 0;
-        const bool need_vel = NDIM == 3 ? (m >= z0 + 1) : true;
-        if (need_vel) {
-            int fz = 0;
-            const int az = NDIM == 3 ? map_index(vpl, nz, gp.bc_lo[2], gp.bc_hi[2], fz) : 0;
-            // every round's loads first (lanes without a tile cell load their
-            // own cell), then the velocities
-            T vr[RV][NDIM + 1];
-#pragma unroll
-            for (int r = 0; r < RV; r++) {
-                const int c = az * plane + (vcode[r] >= 0 ? vcode[r] : own_off);
-#pragma unroll
-                for (int a = 0; a <= NDIM; a++) vr[r][a] = Wf[a][c];
-            }
-#pragma unroll
-            for (int r = 0; r < RV; r++) {
-                if (vcode[r] < 0) continue;
-                const int li = tid + r * NT;
-                const unsigned fl = flips >> (2 * (RC + r));
-                const T rho = vr[r][0];
-                T mxv = vr[r][1];
-                if (fl & 1) mxv = -mxv;
-#ifdef PPML_EXACT
-                s_vx[slot][li] = mxv / rho;
-#else
-                const T ir = fast_rcp(rho);
-                s_vx[slot][li] = mxv * ir;
-#endif
-                if constexpr (NDIM >= 2) {
-                    T myv = vr[r][2];
-                    if (fl & 2) myv = -myv;
-#ifdef PPML_EXACT
-                    s_vy[slot][li] = myv / rho;
-#else
-                    s_vy[slot][li] = myv * ir;
-#endif
-                }
-                if constexpr (NDIM == 3) {
-                    T mzv = vr[r][3];
-                    if (fz) mzv = -mzv;
-#ifdef PPML_EXACT
-                    s_vz[zslot][li] = mzv / rho;
-#else
-                    s_vz[zslot][li] = mzv * ir;
-#endif
-                }
-            }
-            if (gp.any_inflow) {
-                // ghosts of inflow faces take the face's state: a z face (the
-                // last axis filled) overrides x and y; after an x or y face
-                // only the later reflections (y, z) apply
-                const int fzi = NDIM == 3 ? inflow_face(vpl, nz, gp.bc_lo[2], gp.bc_hi[2], 2) : -1;
-#pragma unroll 1
-                for (int r = 0; r < RV; r++) {
-                    const unsigned io = (flips >> (16 + 3 * (RC + r))) & 7u;
-                    if (vcode[r] < 0 || (io == 0 && fzi < 0)) continue;
-                    const int li = tid + r * NT;
-                    const int face = fzi >= 0 ? fzi : (int)io - 1;
-                    const unsigned fl = fzi >= 0 ? 0u : (io >= 3 ? 0u : (flips >> (2 * (RC + r))) & 2u);
-                    const bool flz = fzi < 0 && fz;
-                    const T rho = inflow_value<T>(ctrl, face, 0);
-                    const T mxv = inflow_value<T>(ctrl, face, 1);
-#ifdef PPML_EXACT
-                    s_vx[slot][li] = mxv / rho;
-#else
-                    const T ir = fast_rcp(rho);
-                    s_vx[slot][li] = mxv * ir;
-#endif
-                    if constexpr (NDIM >= 2) {
-                        T myv = inflow_value<T>(ctrl, face, 2);
-                        if (fl & 2) myv = -myv;
-#ifdef PPML_EXACT
-                        s_vy[slot][li] = myv / rho;
-#else
-                        s_vy[slot][li] = myv * ir;
-#endif
-                    }
-                    if constexpr (NDIM == 3) {
-                        T mzv = inflow_value<T>(ctrl, face, 3);
-                        if (flz) mzv = -mzv;
-#ifdef PPML_EXACT
-                        s_vz[zslot][li] = mzv / rho;
-#else
-                        s_vz[zslot][li] = mzv * ir;
-#endif
-                    }
-                }
-            }
-        }
-
-        if constexpr (NDIM == 3) {
-            // own column, plane m, every field: z parabola of cell m-2
-#pragma unroll
-            for (int f = 0; f < NF; f++) {
-                T v = ov[f];
-                if (f == 3 && fzo) v = -v;
-                q0[f] = q1[f];
-                q1[f] = q2[f];
-                q2[f] = v;
-                const T dnew = limited_slope(q0[f], q1[f], q2[f]);
-                const T qInew = interface_value(q0[f], q1[f], dmq[f], dnew);
-                pnw[f] = profile(gp.first_order, q0[f], qI[f], qInew);
-                dmq[f] = dnew;
-                qI[f] = qInew;
-            }
-            sz0 = sz1; sz1 = sz2; sz2 = sz3; sz3 = dsqrt(q2[0]);
-            // the cross tile of plane k, sent one plane ago, is completed
-            // before the barrier below, which also orders it for the x / y
-            // jobs of the plane
-            if constexpr (PIPE)
-                if (k >= z0) fix_cross(k);
-            if (need_vel) {
-                __syncthreads();
-                // transverse velocity of the own column at plane m-2
-                const T *V = s_vz[zslot];
-                const int l = (ty + 1) * VW + tx + 1;
-                const T vt = tmpl9(V[l + 1 + VW], V[l + 1 - VW], V[l - 1 + VW], V[l - 1 - VW], V[l + 1], V[l - 1],
-                                   V[l + VW], V[l - VW], V[l]);
-                // interface between planes m-3 and m-2
-                const T vh = interface_velocity(vtz_prev, sz0, vt, sz1);
-#ifdef PPML_EXACT
-                const T z = dabs(vh) * tau / hz;
-#pragma unroll
-                for (int f = 0; f < NF; f++) {
-                    const T F = upwind_flux(vh, z, ppv[f], pnw[f]);
-                    DFz[f] = (F - Fzp[f]) / hz;
-                    Fzp[f] = F;
-                }
-#else
-                // fluxes times tau / h_z: the update subtracts their differences
-                const bool up = vh >= T(0);
-                const FaceW<T> w = face_weights(gp.first_order, up, vh * tohz);
-#pragma unroll
-                for (int f = 0; f < NF; f++) {
-                    const Prof &a = ppv[f], &b = pnw[f];
-                    const T F = face_flux(w, Prof{up ? a.dl : b.dl, up ? a.dr : b.dr, up ? a.c : b.c});
-                    DFz[f] = F - Fzp[f];
-                    Fzp[f] = F;
-                }
-#endif
-                vtz_prev = vt;
-            }
-            if (k < z0) return;  // warm-up: uniform over the block
-        } else {
-            __syncthreads();
-        }
-
-        // ---- x / y directions of plane k, G fields per pass ----
-        T (*sf)[PS] = s_f[PIPE ? (k & 1) : 0];  // cross tile of plane k
-        T acc[NF];
-        T own[NF];  // U^{n+1/2} of the thread's own cell, read from the tiles
-        // flux jobs: round 0 the x interfaces 0 .. NT-1, round 1 the y
-        // interfaces 0 .. NT-1, the last round the remaining x interfaces
-        // (wave 0) and y interfaces (wave 1): no wave takes both kinds in one
-        // round or more than three jobs, and the kind of the first two rounds
-        // is known at compile time
-        static_assert(NXI >= NT && NXI - NT <= 64 && (NDIM < 2 || (NYI >= NT && NYI - NT <= 64 && NT >= 128)),
-                      "flux job rounds");
-        constexpr int NJF = NDIM >= 2 ? 3 : 2;
-        auto flux_job = [&](int r) -> int {
-            if (r == 0) return tid;
-            if (NDIM >= 2 && r == 1) return NXI + tid;
-            if (wv == 0) return NT + ln < NXI ? NT + ln : NXI + NYI;
-            if (NDIM >= 2 && wv == 1) return NXI + NT + ln;
-            return NXI + NYI;
+    // FP32 3-D takes two planes per trip with the two sets of profiles of
+    // the previous cell exchanged, so that no profile is copied from one
+    // plane to the next; an odd count of planes starts one plane lower, whose
+    // state reaches only warm-up planes.  Otherwise one plane per trip and a
+    // copy of the new profiles.
+    constexpr bool TWO = NDIM == 3 && sizeof(T) == 4;
+    if constexpr (TWO) {
+        Prof pB[NF];
+        auto plane_step = [&](const int m, Prof(&pprev)[NF], Prof(&pnew)[NF]) __attribute__((always_inline)) {
+            do {  // `continue` in the plane's body leaves it
+#include "ppml_lagr_plane.inc"
+            } while (false);
         };
-        T vhr[NJF];  // interface velocities of this thread's flux jobs
-        // velocity ring slots of planes k-1, k, k+1
-        const int sm = NDIM == 3 ? ((k - 1) % 3 + 3) % 3 : 0;
-        const int s0 = NDIM == 3 ? (k % 3 + 3) % 3 : 0;
-        const int sp = NDIM == 3 ? ((k + 1) % 3 + 3) % 3 : 0;
-        (void)sm;
-        (void)s0;
-        (void)sp;
-#pragma unroll
-        for (int pass = 0; pass < NPASS; pass++) {
-            const int f0 = pass * G;
-            // the previous pass reads its tile (own cell values) after its last
-            // barrier: every wave must be done before the tile is overwritten
-            if (pass > 0) __syncthreads();
-            if constexpr (!PIPE) {
-                // cross tiles of the pass's fields
-#pragma unroll
-                for (int r = 0; r < RC; r++) {
-                    if (ccode[r] < 0) continue;
-                    const int li = tid + r * NT;
-                    const unsigned fl = flips >> (2 * r);
-                    const int c = k * plane + ccode[r];
-#pragma unroll
-                    for (int g = 0; g < G; g++) {
-                        const int f = f0 + g;
-                        if (f >= NF) break;
-                        T v = Wf[f][c];
-                        if ((f == 1 && (fl & 1)) || (NDIM >= 2 && f == 2 && (fl & 2))) v = -v;
-                        sf[g][li] = v;
-                    }
-                }
-                if (gp.any_inflow) {
-                    // ghosts of inflow faces take the face's state (a y face
-                    // comes after any x reflection)
-#pragma unroll
-                    for (int r = 0; r < RC; r++) {
-                        const unsigned io = (flips >> (16 + 3 * r)) & 7u;
-                        if (ccode[r] < 0 || io == 0) continue;
-                        const int li = tid + r * NT;
-                        const unsigned fl = io >= 3 ? 0u : (flips >> (2 * r)) & 2u;
-#pragma unroll
-                        for (int g = 0; g < G; g++) {
-                            const int f = f0 + g;
-                            if (f >= NF) break;
-                            T v = inflow_value<T>(ctrl, io - 1, inflow_component<NDIM>(f));
-                            if (NDIM >= 2 && f == 2 && (fl & 2)) v = -v;
-                            sf[g][li] = v;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-            // interface values (Appendix step 1) at every face of the tile.  In
-            // FP64, two neighbouring faces per job share the limited slope of
-            // the cell between them (3 slopes for 2 faces; the last job of a
-            // row or column may hold one face); the FP32 kernel, at its
-            // register limit, takes one cell per job and shares slopes between
-            // neighbouring lanes.
-            if constexpr (sizeof(T) == 8) {
-                constexpr int PXR = (TX + 4) / 2;             // x jobs per row
-                constexpr int PYC = (TY + 4) / 2;             // y jobs per column
-                constexpr int NPX = PXR * TY;
-                constexpr int NPY = NDIM >= 2 ? PYC * TX : 0;
-                for (int j = tid; j < NPX + NPY; j += NT) {
-                    if (j < NPX) {
-                        const int p = j % PXR, cy = j / PXR;
-                        const int fxi = 2 * p;                    // faces fxi, fxi + 1
-                        const bool two = fxi + 1 <= TX + 2;
-                        const int l = (cy + HY) * PW + fxi;       // q of tile-rel cells fxi-3 .. fxi+1
-                        const int o = cy * (TX + 3) + fxi;
-#pragma unroll
-                        for (int g = 0; g < G; g++) {
-                            if (f0 + g >= NF) break;
-                            const T *q = sf[g];
-                            const T da = limited_slope(q[l], q[l + 1], q[l + 2]);
-                            const T db = limited_slope(q[l + 1], q[l + 2], q[l + 3]);
-                            s_qx[g][o] = interface_value(q[l + 1], q[l + 2], da, db);
-                            if (two) {
-                                const T dc = limited_slope(q[l + 2], q[l + 3], q[l + 4]);
-                                s_qx[g][o + 1] = interface_value(q[l + 2], q[l + 3], db, dc);
-                            }
-                        }
-                    } else if constexpr (NDIM >= 2) {
-                        const int jj = j - NPX;
-                        const int cx = jj % TX, fyi = 2 * (jj / TX);  // faces fyi, fyi + 1
-                        const bool two = fyi + 1 <= TY + 2;
-                        const int l = fyi * PW + cx + HX;            // rows fyi-3 .. fyi+1 (tile-rel)
-#pragma unroll
-                        for (int g = 0; g < G; g++) {
-                            if (f0 + g >= NF) break;
-                            const T *q = sf[g];
-                            const T da = limited_slope(q[l], q[l + PW], q[l + 2 * PW]);
-                            const T db = limited_slope(q[l + PW], q[l + 2 * PW], q[l + 3 * PW]);
-                            s_qy[g][cx * (TY + 3) + fyi] = interface_value(q[l + PW], q[l + 2 * PW], da, db);
-                            if (two) {
-                                const T dc = limited_slope(q[l + 2 * PW], q[l + 3 * PW], q[l + 4 * PW]);
-                                s_qy[g][cx * (TY + 3) + fyi + 1] = interface_value(q[l + 2 * PW], q[l + 3 * PW], db, dc);
-                            }
-                        }
-                    }
-                }
-            } else {
-                // One job per cell of a row (x) or column (y) of the tile and
-                // its halo: the lane takes the limited slope of its cell, the
-                // slope of the previous cell of the line from the previous
-                // lane of its 16-lane DPP row, and writes the interface value
-                // between the two cells.  Lane 0 of each DPP row only supplies
-                // the slope of the cell before the row's first cell, so every
-                // slope is computed once per 15 faces rather than twice per
-                // face.  x cells: tile-rel x -2 .. TX+1 (x fastest) of rows
-                // 0 .. TY-1; y cells: tile-rel y -2 .. TY+1 (y fastest) of
-                // columns 0 .. TX-1.
-                constexpr int NXC = (TX + 4) * TY;
-                constexpr int NYC = NDIM >= 2 ? TX * (TY + 4) : 0;
-                constexpr int DX = (NXC + 14) / 15;  // DPP rows of x cells
-                constexpr int DY = (NYC + 14) / 15;
-                using JD = JobMap<NT, DX * 16, DY * 16>;
-                const int t = ln & 15;
-#pragma unroll 1
-                for (int rq = 0; rq < JD::R; rq++) {
-                    const int jd = JD::job(rq, wv, ln);  // DPP-row slot: row jd >> 4, lane t
-                    if (jd >= (DX + DY) * 16) continue;  // whole DPP rows past the last one of a kind
-                    if (jd < DX * 16) {
-                        const int X = (jd >> 4) * 15 + t - 1;
-                        const int Xc = X < 0 ? 0 : (X < NXC ? X : NXC - 1);
-                        const int c = Xc % (TX + 4) - 2, cy = Xc / (TX + 4);
-                        const int l = (cy + HY) * PW + c + HX;
-                        const bool put = t >= 1 && X < NXC && c > -2;
-                        const int o = cy * (TX + 3) + c + 1;  // face between cells c-1 and c
-                        // every field's values and faces first, the stores
-                        // after them, so that no load waits behind a store
-                        T iv[G];
-#pragma unroll
-                        for (int g = 0; g < G; g++) {
-                            if (f0 + g >= NF) break;
-                            const T *q = sf[g];
-                            const T qm = q[l - 1], q0 = q[l];
-                            const T d = limited_slope(qm, q0, q[l + 1]);
-                            iv[g] = interface_value(qm, q0, dpp_prev16(d), d);
-                        }
-                        if (put) {
-#pragma unroll
-                            for (int g = 0; g < G; g++)
-                                if (f0 + g < NF) s_qx[g][o] = iv[g];
-                        }
-                    } else if constexpr (NDIM >= 2) {
-                        const int Y = ((jd >> 4) - DX) * 15 + t - 1;
-                        const int Yc = Y < 0 ? 0 : (Y < NYC ? Y : NYC - 1);
-                        const int r = Yc % (TY + 4) - 2, cx = Yc / (TY + 4);
-                        const int l = (r + HY) * PW + cx + HX;
-                        const bool put = t >= 1 && Y < NYC && r > -2;
-                        const int o = cx * (TY + 3) + r + 1;  // face between rows r-1 and r
-                        T iv[G];
-#pragma unroll
-                        for (int g = 0; g < G; g++) {
-                            if (f0 + g >= NF) break;
-                            const T *q = sf[g];
-                            const T qm = q[l - PW], q0 = q[l];
-                            const T d = limited_slope(qm, q0, q[l + PW]);
-                            iv[g] = interface_value(qm, q0, dpp_prev16(d), d);
-                        }
-                        if (put) {
-#pragma unroll
-                            for (int g = 0; g < G; g++)
-                                if (f0 + g < NF) s_qy[g][o] = iv[g];
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-            // upwind fluxes: only the upwind cell's parabola is needed.  They
-            // are kept in registers until every job has read the face values,
-            // then stored over the face arrays.
-            T Fr[NJF][G];
-#pragma unroll
-            for (int r = 0; r < NJF; r++) {
-                const int j = flux_job(r);
-                if (j < NXI) {
-                    const int ix = j % (TX + 1), cy = j / (TX + 1);
-                    if (pass == 0) {
-                        // interface velocity: 9-point transverse velocity of
-                        // both cells, weighted by sqrt(rho) (Sec. 2.3)
-                        T vt[2];
-#pragma unroll
-                        for (int u = 0; u < 2; u++) {
-                            const int l = (cy + 1) * VW + ix + u;  // tile-rel x = ix-1+u
-                            if constexpr (NDIM == 3) {
-                                const T *A = s_vx[sm], *B = s_vx[s0], *C = s_vx[sp];
-                                // transverse axes y (first) and z (second)
-                                vt[u] = tmpl9(C[l + VW], A[l + VW], C[l - VW], A[l - VW], B[l + VW], B[l - VW], C[l],
-                                              A[l], B[l]);
-                            } else if constexpr (NDIM == 2) {
-                                const T *B = s_vx[0];
-                                vt[u] = tmpl3(B[l + VW], B[l - VW], B[l]);
-                            } else {
-                                vt[u] = s_vx[0][ix + u];
-                            }
-                        }
-                        const int la = (cy + HY) * PW + ix - 1 + HX;
-                        vhr[r] = interface_velocity(vt[0], dsqrt(sf[0][la]), vt[1], dsqrt(sf[0][la + 1]));
-                    }
-                    const T vh = vhr[r];
-                    const bool left = vh >= T(0);
-                    const int u = left ? ix - 1 : ix;             // tile-rel upwind cell
-                    const int lq = (cy + HY) * PW + u + HX;       // its value
-                    const int lf = cy * (TX + 3) + u + 1;         // its left face
-#ifdef PPML_EXACT
-                    const T z = dabs(vh) * tau / hx;
-#pragma unroll
-                    for (int g = 0; g < G; g++) {
-                        if (f0 + g >= NF) break;
-                        const Parab<T> p = profile(gp.first_order, sf[g][lq], s_qx[g][lf], s_qx[g][lf + 1]);
-                        const T fs = left ? avg_left(p.L, p.R, p.Q6, z) : avg_right(p.L, p.R, p.Q6, z);
-                        Fr[r][g] = vh * fs;
-                    }
-#else
-                    const FaceW<T> w = face_weights(gp.first_order, left, vh * tohx);  // fluxes times tau / h_x
-#pragma unroll
-                    for (int g = 0; g < G; g++) {
-                        if (f0 + g >= NF) break;
-                        Fr[r][g] = face_flux(w, mono_jumps(sf[g][lq], s_qx[g][lf], s_qx[g][lf + 1]));
-                    }
-#endif
-                } else if (NDIM >= 2 && j < NXI + NYI) {
-                    const int jj = j - NXI;
-                    const int cx = jj % TX, iy = jj / TX;
-                    if (pass == 0) {
-                        T vt[2];
-#pragma unroll
-                        for (int u = 0; u < 2; u++) {
-                            const int l = (iy + u) * VW + cx + 1;  // tile-rel y = iy-1+u
-                            if constexpr (NDIM == 3) {
-                                const T *A = s_vy[sm], *B = s_vy[s0], *C = s_vy[sp];
-                                // transverse axes x (first) and z (second)
-                                vt[u] = tmpl9(C[l + 1], A[l + 1], C[l - 1], A[l - 1], B[l + 1], B[l - 1], C[l], A[l],
-                                              B[l]);
-                            } else {
-                                const T *B = s_vy[0];
-                                vt[u] = tmpl3(B[l + 1], B[l - 1], B[l]);
-                            }
-                        }
-                        const int la = (iy - 1 + HY) * PW + cx + HX;
-                        vhr[r] = interface_velocity(vt[0], dsqrt(sf[0][la]), vt[1], dsqrt(sf[0][la + PW]));
-                    }
-                    const T vh = vhr[r];
-                    const bool left = vh >= T(0);
-                    const int u = left ? iy - 1 : iy;
-                    const int lq = (u + HY) * PW + cx + HX;
-                    const int lf = cx * (TY + 3) + u + 1;
-#ifdef PPML_EXACT
-                    const T z = dabs(vh) * tau / hy;
-#pragma unroll
-                    for (int g = 0; g < G; g++) {
-                        if (f0 + g >= NF) break;
-                        const Parab<T> p = profile(gp.first_order, sf[g][lq], s_qy[g][lf], s_qy[g][lf + 1]);
-                        const T fs = left ? avg_left(p.L, p.R, p.Q6, z) : avg_right(p.L, p.R, p.Q6, z);
-                        Fr[r][g] = vh * fs;
-                    }
-#else
-                    const FaceW<T> w = face_weights(gp.first_order, left, vh * tohy);  // fluxes times tau / h_y
-#pragma unroll
-                    for (int g = 0; g < G; g++) {
-                        if (f0 + g >= NF) break;
-                        Fr[r][g] = face_flux(w, mono_jumps(sf[g][lq], s_qy[g][lf], s_qy[g][lf + 1]));
-                    }
-#endif
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < NJF; r++) {
-                const int j = flux_job(r);
-                if (j < NXI) {
-#pragma unroll
-                    for (int g = 0; g < G; g++)
-                        if (f0 + g < NF) s_Fx[g][j] = Fr[r][g];
-                } else if (NDIM >= 2 && j < NXI + NYI) {
-#pragma unroll
-                    for (int g = 0; g < G; g++)
-                        if (f0 + g < NF) s_Fy[g][j - NXI] = Fr[r][g];
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int g = 0; g < G; g++) {
-                const int f = f0 + g;
-                if (f >= NF) break;
-                own[f] = sf[g][(ty + HY) * PW + tx + HX];
-#ifdef PPML_EXACT
-                T a = (s_Fx[g][ty * (TX + 1) + tx + 1] - s_Fx[g][ty * (TX + 1) + tx]) / hx;
-                if constexpr (NDIM >= 2) a = a + (s_Fy[g][(ty + 1) * TX + tx] - s_Fy[g][ty * TX + tx]) / hy;
-#else
-                // (the product build's fluxes carry the factor tau / h)
-                T a = s_Fx[g][ty * (TX + 1) + tx + 1] - s_Fx[g][ty * (TX + 1) + tx];
-                if constexpr (NDIM >= 2) a = a + (s_Fy[g][(ty + 1) * TX + tx] - s_Fy[g][ty * TX + tx]);
-#endif
-                if constexpr (NDIM == 3) a = a + DFz[f];
-                acc[f] = a;
-            }
-        }
-        // This wave's last read of a cross tile in this plane is done, and
-        // every wave is past the previous plane: the previous plane's buffer
-        // takes the next plane's cross tile, whose transfer overlaps the
-        // update below and the next plane's z arithmetic.  (Issued after the
-        // last tile read, so that no LDS read of this plane waits for it.)
-        if constexpr (PIPE)
-            if (k + 1 < z1) dma_cross(k + 1);
-
-        if (valid) {
-            const int c = k * plane + gy * nx + gx;
-            T fn[NF];
-#pragma unroll
-            for (int f = 0; f < NF; f++)
-#ifdef PPML_EXACT
-                fn[f] = own[f] - tau * acc[f];
-#else
-                fn[f] = own[f] - acc[f];
-#endif
-            // total-energy correction (Sec. 2.4), FP64 arithmetic
-            const double r = (double)fn[0];
-            double mx = (double)fn[1];
-            double my = NDIM >= 2 ? (double)fn[2] : 0.0;
-            double mz = NDIM >= 3 ? (double)fn[3] : 0.0;
-            const double Et = (double)fn[NDIM + 1];
-            double e = (double)fn[NDIM + 2];
-            if (r < thr) {
-                const double E = Et / r, eps = e / r;
-                const double w = __builtin_sqrt(mx * mx + my * my + mz * mz) / r;
-                if (E > eps && w > 0.0) {
-                    const double sc = __builtin_sqrt(2.0 * (E - eps)) / w;
-                    fn[1] = (T)(mx * sc);
-                    if constexpr (NDIM >= 2) fn[2] = (T)(my * sc);
-                    if constexpr (NDIM >= 3) fn[3] = (T)(mz * sc);
-                } else {
-                    fn[1] = T(0);
-                    if constexpr (NDIM >= 2) fn[2] = T(0);
-                    if constexpr (NDIM >= 3) fn[3] = T(0);
-                    fn[NDIM + 2] = (T)Et;
-                }
-            } else {
-#ifdef PPML_EXACT
-                const double kin = (mx * mx + my * my + mz * mz) / (2.0 * r);
-#else
-                const double kin = (mx * mx + my * my + mz * mz) * (0.5 * fast_rcp(r));
-#endif
-                const double d = Et - kin;
-                if (d > 0.0) fn[NDIM + 2] = (T)d;
-            }
-#pragma unroll
-            for (int f = 0; f < NF; f++) U[(size_t)f * (size_t)N + c] = fn[f];
-            T v, cs;
-            cell_speeds<T, NDIM>(fn[0], fn[1], NDIM >= 2 ? fn[2] : T(0), NDIM >= 3 ? fn[3] : T(0), fn[NDIM + 2], prho,
-                                 gam, gm1, v, cs);
-            const bool bad = !(fn[0] > T(0)) || !(fn[NDIM + 2] > T(0)) || !(v == v) || !(cs == cs) ||
-                             __builtin_isinf(v) || __builtin_isinf(fn[NDIM + 1]);
-            if (bad) atomicOr(&ctrl->err, 1);
-            vmax = vmax > v ? vmax : v;
-            cmax = cmax > cs ? cmax : cs;
-        }
-    };
-    // FP32 3-D: two planes per trip with the profile sets exchanged, so that
-    // no profile is copied from one plane to the next; an odd count of
-    // planes starts one plane lower, whose state only reaches warm-up planes.
-    // Otherwise one plane per trip and a copy.
-    if constexpr (NDIM == 3 && sizeof(T) == 4) {
-        for (int m = ((m_end - m_beg) & 1) ? m_beg - 1 : m_beg; m < m_end; m += 2) {
+        for (int m = (m_end - m_beg) & 1 ? m_beg - 1 : m_beg; m < m_end; m += 2) {
             plane_step(m, pprev, pB);
             plane_step(m + 1, pB, pprev);
         }
     } else {
         for (int m = m_beg; m < m_end; ++m) {
-            plane_step(m, pprev, pB);
-#pragma unroll
-            for (int f = 0; f < NF; f++) pprev[f] = pB[f];
+            Prof pnew[NF];
+            (void)pnew;
+#include "ppml_lagr_plane.inc"
         }
     }
     publish_max(ctrl, sl ^ 1, (double)vmax, (double)cmax);
