@@ -55,8 +55,9 @@ ALGO_FLOP_PER_ZONE_3D = {"euler": 362, "lagr": 781}
 # FP64; the published FP32 figure (157.3) assumes packed FP32.
 VALU_PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_box256.json")
-KERNEL_SOURCES = ("paper_1607_01105_amd/csrc/ppml_kernels.hpp", "paper_1607_01105_amd/csrc/ppml_lagr_plane.inc",
-                  "paper_1607_01105_amd/csrc/ppml_device.hpp", "paper_1607_01105_amd/build.py")
+KERNEL_SOURCES = ("paper_1607_01105_amd/csrc/ppml_kernels.hpp", "paper_1607_01105_amd/csrc/ppml_euler_plane.inc",
+                  "paper_1607_01105_amd/csrc/ppml_lagr_plane.inc", "paper_1607_01105_amd/csrc/ppml_device.hpp",
+                  "paper_1607_01105_amd/build.py")
 
 
 def measured_counters(kernel_key: str):

@@ -412,267 +412,45 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
 
     const int m_beg = NDIM == 3 ? z0 - 3 : 0;
     const int m_end = NDIM == 3 ? z1 + 3 : 1;
-    for (int m = m_beg; m < m_end; ++m) {
-        const int k = NDIM == 3 ? m - 3 : 0;
-        T DPz = 0, DPVz = 0, DVz = 0;
-        // FP32 without self-gravity: every load of the iteration is issued
-        // before any of its values is used, so that the iteration costs one
-        // memory latency: the own column at plane m (3-D), then, past the
-        // warm-up planes, the cross tile of plane k (lanes without a cross
-        // cell load their own cell) and the own cell of plane k for the
-        // update.  FP64 and the self-gravity kernels, whose registers are
-        // scarcer, issue the cross tile after the z arithmetic and the own
-        // cell in the update.
-        constexpr bool EARLY = sizeof(T) == 4 && XF == 0;
-        const bool live = k >= z0;
-        int fz = 0;
-        T zr[3] = {T(1), T(1), T(1)};  // rho, m_z, rho*eps of the column at plane m
-        if constexpr (NDIM == 3) {
-            const int mz = map_index(m, nz, gp.bc_lo[2], gp.bc_hi[2], fz);
-            const int c = mz * plane + cy_ * nx + cx_;
-            zr[0] = Uf[0][c];
-            zr[1] = Uf[3][c];
-            zr[2] = Uf[5][c];
-        }
-        T xr[RC][NDIM + 2];  // rho, m_x, (m_y), rho*eps
-        T uo[NF];            // U^n of the own cell
-        auto load_cross = [&]() {
-#pragma unroll
-            for (int r = 0; r < RC; r++) {
-                const int c = k * plane + (ccode[r] >= 0 ? ccode[r] : own_off);
-                xr[r][0] = Uf[0][c];
-                xr[r][1] = Uf[1][c];
-                if constexpr (NDIM >= 2) xr[r][2] = Uf[2][c];
-                xr[r][NDIM + 1] = Uf[2 + NDIM][c];
-            }
+    // FP32 3-D without self-gravity takes two planes per trip with the two
+    // pairs of z profiles exchanged (every tile shape, so that they all give
+    // the same bits); an odd count of planes starts one plane lower, whose
+    // state reaches only warm-up planes.  Tiles of at least eight rows, which
+    // hold the extra registers without spilling, also load the own column
+    // one plane ahead, so that a plane's z arithmetic need not wait for
+    // memory.  Otherwise one plane per trip.
+    constexpr bool TWO = NDIM == 3 && sizeof(T) == 4 && XF == 0;
+    constexpr bool ZPRE = TWO && TY >= 8;
+    if constexpr (TWO) {
+        T zn0 = 1, zn1 = 1, zn2 = 1;  // rho, m_z, rho*eps of the column, one plane ahead
+        int fzn = 0;
+        auto load_column = [&](const int mm) {
+            const int c = map_index(mm, nz, gp.bc_lo[2], gp.bc_hi[2], fzn) * plane + own_off;
+            zn0 = Uf[0][c];
+            zn1 = Uf[3][c];
+            zn2 = Uf[5][c];
         };
-        auto load_own = [&]() {
-            const int c = k * plane + gy * nx + gx;
-#pragma unroll
-            for (int f = 0; f < NF; f++) uo[f] = Uf[f][c];
+        Profile<T> pvB = pv_prev, ppB = pp_prev;
+        auto plane_step = [&](const int m, Profile<T> &pv_prev, Profile<T> &pp_prev, Profile<T> &pv_next,
+                              Profile<T> &pp_next) __attribute__((always_inline)) {
+            do {  // `continue` in the plane's body leaves it
+#include "ppml_euler_plane.inc"
+            } while (false);
         };
-        if (EARLY && live) {
-            load_cross();
-            if (valid) load_own();
+        const int m_first = (m_end - m_beg) & 1 ? m_beg - 1 : m_beg;
+        if constexpr (ZPRE) load_column(m_first);
+        for (int m = m_first; m < m_end; m += 2) {
+            plane_step(m, pv_prev, pp_prev, pvB, ppB);
+            plane_step(m + 1, pvB, ppB, pv_prev, pp_prev);
         }
-        if constexpr (NDIM == 3) {
-            T rho = zr[0];
-            T mzv = zr[1];
-            if (fz) mzv = -mzv;
-            T e = zr[2];
-            if (gp.any_inflow) {  // plane m is a ghost of an inflow z face
-                const int fzi = inflow_face(m, nz, gp.bc_lo[2], gp.bc_hi[2], 2);
-                if (fzi >= 0) {
-                    rho = inflow_value<T>(ctrl, fzi, 0);
-                    mzv = inflow_value<T>(ctrl, fzi, 3);
-                    e = inflow_value<T>(ctrl, fzi, 5);
-                }
-            }
-#ifdef PPML_EXACT
-            const T vz = mzv / rho;
-#else
-            const T vz = mzv * fast_rcp(rho);
-#endif
-            const T p = prho * rho + gm1 * e;
-            const T s = dsqrt(rho);
-            qv0 = qv1; qv1 = qv2; qv2 = vz;
-            qp0 = qp1; qp1 = qp2; qp2 = p;
-            sr0 = sr1; sr1 = sr2; sr2 = sr3; sr3 = s;
-            rr0 = rr1; rr1 = rr2; rr2 = rr3; rr3 = rho * s;
-            pr0 = pr1; pr1 = pr2; pr2 = pr3; pr3 = p * s;
-            const T dv_new = limited_slope(qv0, qv1, qv2);
-            const T dp_new = limited_slope(qp0, qp1, qp2);
-            const T qIv_new = interface_value(qv0, qv1, dmv, dv_new);
-            const T qIp_new = interface_value(qp0, qp1, dmp, dp_new);
-            const Profile<T> pv_new = profile(gp.first_order, qv0, qIv, qIv_new);
-            const Profile<T> pp_new = profile(gp.first_order, qp0, qIp, qIp_new);
-            dmv = dv_new; dmp = dp_new; qIv = qIv_new; qIp = qIp_new;
-            // interface between planes m-3 and m-2
-            const VP<T> vpz = riemann(gp.first_order, sr0, sr1, rr0, rr1, pr0, pr1, pv_prev, pv_new, pp_prev, pp_new, gam, tau, hz,
-                                      tohz);
-            DPz = PPML_DIV(vpz.P - Pprev, hz, ihz);
-            DPVz = PPML_DIV(vpz.P * vpz.V - Pprev * Vprev, hz, ihz);
-            DVz = PPML_DIV(vpz.V - Vprev, hz, ihz);
-            Vprev = vpz.V;
-            Pprev = vpz.P;
-            pv_prev = pv_new;
-            pp_prev = pp_new;
-            if (k < z0) continue;  // warm-up planes: uniform over the block
-        }
-
-        // ---- x / y directions of plane k from LDS ----
-        if constexpr (!EARLY) load_cross();
-        // overlaid tiles: the previous plane's update has read its interface
-        // states before they are overwritten (the loads above are in flight)
-        if constexpr (OVERLAY) __syncthreads();
-#pragma unroll
-        for (int r = 0; r < RC; r++) {
-            if (ccode[r] < 0) continue;
-            const int li = tid + r * NT;
-            const unsigned fl = flips >> (2 * r);
-            const T rho = xr[r][0];
-            T mxv = xr[r][1];
-            if (fl & 1) mxv = -mxv;
-            const T e = xr[r][NDIM + 1];
-#ifdef PPML_EXACT
-            s_vx[li] = mxv / rho;
-#else
-            const T ir = fast_rcp(rho);
-            s_vx[li] = mxv * ir;
-#endif
-            if constexpr (NDIM >= 2) {
-                T myv = xr[r][2];
-                if (fl & 2) myv = -myv;
-#ifdef PPML_EXACT
-                s_vy[li] = myv / rho;
-#else
-                s_vy[li] = myv * ir;
-#endif
-            }
-            const T p = prho * rho + gm1 * e;
-            const T s = dsqrt(rho);
-            s_p[li] = p;
-            s_s[li] = s;
-            s_r32[li] = rho * s;
-            s_ps[li] = p * s;
-        }
-        if (gp.any_inflow) {
-            // ghosts of inflow faces take the face's state (a y face comes
-            // after any x reflection, so only later flips apply)
-#pragma unroll
-            for (int r = 0; r < RC; r++) {
-                const unsigned io = (flips >> (16 + 3 * r)) & 7u;
-                if (ccode[r] < 0 || io == 0) continue;
-                const int li = tid + r * NT;
-                const unsigned fl = io >= 3 ? 0u : (flips >> (2 * r)) & 2u;
-                const T rho = inflow_value<T>(ctrl, io - 1, 0);
-                const T e = inflow_value<T>(ctrl, io - 1, 5);
-                const T mxv = inflow_value<T>(ctrl, io - 1, 1);
-#ifdef PPML_EXACT
-                s_vx[li] = mxv / rho;
-#else
-                const T ir = fast_rcp(rho);
-                s_vx[li] = mxv * ir;
-#endif
-                if constexpr (NDIM >= 2) {
-                    T myv = inflow_value<T>(ctrl, io - 1, 2);
-                    if (fl & 2) myv = -myv;
-#ifdef PPML_EXACT
-                    s_vy[li] = myv / rho;
-#else
-                    s_vy[li] = myv * ir;
-#endif
-                }
-                const T p = prho * rho + gm1 * e;
-                const T s = dsqrt(rho);
-                s_p[li] = p;
-                s_s[li] = s;
-                s_r32[li] = rho * s;
-                s_ps[li] = p * s;
-            }
-        }
-        __syncthreads();
-        // parabolas of v_d and p, a run of NC cells of one field per job
-        // (slopes and interface values shared inside the run): x runs of each
-        // row (v_x, then p), then y runs of each column (v_y, then p), in one
-        // job space
-        using JP = JobMap<NT, 2 * NXR, 2 * NYR>;
-#pragma unroll 1
-        for (int rq = 0; rq < JP::R; rq++) {
-            const int j = JP::job(rq, wv, ln);
-            if (j < 2 * NXR) {
-                const bool fp = j >= NXR;
-                const int jr = fp ? j - NXR : j;
-                const int rx = jr % RXN, cy = jr / RXN;
-                const int cx = NC * rx < TX + 2 - NC ? NC * rx : TX + 2 - NC;  // first cell (tile-rel x = cx - 1)
-                const int li = (cy + HY) * PW + cx + 2;
-                const int o = cy * (TX + 2) + cx;
-                parabola_run<NC, 1, 1>(gp.first_order, (fp ? s_p : s_vx) + li, (fp ? xp : xv) + o);
-            } else if (NDIM >= 2 && j < 2 * (NXR + NYR)) {
-                const int jj = j - 2 * NXR;
-                const bool fp = jj >= NYR;
-                const int jr = fp ? jj - NYR : jj;
-                const int cx = jr % TX, ry = jr / TX;
-                const int cy = NC * ry < TY + 2 - NC ? NC * ry : TY + 2 - NC;  // first cell (tile-rel y = cy - 1)
-                const int li = (cy - 1 + HY) * PW + cx + HX;
-                const int o = cy * TX + cx;
-                parabola_run<NC, PW, TX>(gp.first_order, (fp ? s_p : s_vy) + li, (fp ? yp : yv) + o);
-            }
-        }
-        __syncthreads();
-        // Riemann problems: x interfaces, then y interfaces, each spread over
-        // the waves so that the wave with a partial x round is not the one
-        // with the partial y round
-        using JR = JobMap<NT, NXI, NDIM >= 2 ? NYI : 0>;
-        for (int qw = wv; qw < JR::QA; qw += JR::NW) {
-            const int j = qw * 64 + ln;
-            if (j >= NXI) continue;
-            const int ix = j % (TX + 1), cy = j / (TX + 1);
-            const int la = (cy + HY) * PW + ix - 1 + HX, lb = la + 1;
-            const int pa = cy * (TX + 2) + ix, pb = pa + 1;
-            xi[j] = riemann(gp.first_order, s_s[la], s_s[lb], s_r32[la], s_r32[lb], s_ps[la], s_ps[lb], xv[pa], xv[pb], xp[pa], xp[pb],
-                            gam, tau, hx, tohx);
-        }
-        if constexpr (NDIM >= 2) {
-            for (int qw = JR::first_b(wv); qw < JR::QA + JR::QB; qw += JR::NW) {
-                const int j = (qw - JR::QA) * 64 + ln;
-                if (j >= NYI) continue;
-                const int cx = j % TX, iy = j / TX;
-                const int la = (iy - 1 + HY) * PW + cx + HX, lb = la + PW;
-                const int pa = iy * TX + cx, pb = pa + TX;
-                yi[j] = riemann(gp.first_order, s_s[la], s_s[lb], s_r32[la], s_r32[lb], s_ps[la], s_ps[lb], yv[pa], yv[pb], yp[pa],
-                                yp[pb], gam, tau, hy, tohy);
-            }
-        }
-        __syncthreads();
-
-        if (valid) {
-            const VP<T> a = xi[ty * (TX + 1) + tx], b = xi[ty * (TX + 1) + tx + 1];
-            const T DPx = PPML_DIV(b.P - a.P, hx, ihx);
-            T sPV = PPML_DIV(b.P * b.V - a.P * a.V, hx, ihx);
-            T sV = PPML_DIV(b.V - a.V, hx, ihx);
-            T DPy = 0;
-            if constexpr (NDIM >= 2) {
-                const VP<T> c0 = yi[ty * TX + tx], c1 = yi[(ty + 1) * TX + tx];
-                DPy = PPML_DIV(c1.P - c0.P, hy, ihy);
-                sPV = sPV + PPML_DIV(c1.P * c1.V - c0.P * c0.V, hy, ihy);
-                sV = sV + PPML_DIV(c1.V - c0.V, hy, ihy);
-            }
-            if constexpr (NDIM == 3) {
-                sPV = sPV + DPVz;
-                sV = sV + DVz;
-            }
-            const int c = k * plane + gy * nx + gx;
-            if constexpr (!EARLY) load_own();
-            const T rho = uo[0];
-            T mom[3];
-            mom[0] = uo[1];
-            mom[1] = NDIM >= 2 ? uo[2] : T(0);
-            mom[2] = NDIM >= 3 ? uo[3] : T(0);
-            const T Et = uo[1 + NDIM];
-            const T e = uo[2 + NDIM];
-            T mn[3];
-            mn[0] = mom[0] - tau * DPx;
-            mn[1] = mom[1] - tau * DPy;
-            mn[2] = mom[2] - tau * DPz;
-            T Etn = Et - tau * sPV;
-            T en = e - ((tau * gm1) * e) * sV;
-            if (XF != 0 || gp.potential != POT_NONE) {
-                double g[3];
-                potential_grad<XF>(gp, gx, gy, k, g);
-                if constexpr (XF != 0 && NDIM == 3)
-                    if (gp.self_grav) self_gravity_grad<T>(gp, gx, gy, k, g);
-                const double work = (double)mom[0] * g[0] + (double)mom[1] * g[1] + (double)mom[2] * g[2];
-                const double tr = tau_d * (double)rho;
-                for (int ax = 0; ax < NDIM; ax++) mn[ax] = (T)((double)mn[ax] - tr * g[ax]);
-                Etn = (T)((double)Etn - tau_d * work);
-            }
-            Wf[0][c] = rho;
-            Wf[1][c] = mn[0];
-            if constexpr (NDIM >= 2) Wf[2][c] = mn[1];
-            if constexpr (NDIM >= 3) Wf[3][c] = mn[2];
-            Wf[1 + NDIM][c] = Etn;
-            Wf[2 + NDIM][c] = en;
+    } else {
+        // stand-ins for the names that only the body's two-plane branches use
+        T zn0, zn1, zn2;
+        int fzn;
+        auto load_column = [](int) {};
+        Profile<T> pv_next, pp_next;
+        for (int m = m_beg; m < m_end; ++m) {
+#include "ppml_euler_plane.inc"
         }
     }
 }
