@@ -412,14 +412,14 @@ __device__ __forceinline__ void euler_body(const T *__restrict__ U, T *__restric
 
     const int m_beg = NDIM == 3 ? z0 - 3 : 0;
     const int m_end = NDIM == 3 ? z1 + 3 : 1;
-    // FP32 3-D without self-gravity takes two planes per trip with the two
-    // pairs of z profiles exchanged (every tile shape, so that they all give
-    // the same bits); an odd count of planes starts one plane lower, whose
+    // FP32 3-D without a halo potential takes two planes per trip with the
+    // two pairs of z profiles exchanged (every tile shape, so that they all
+    // give the same bits); an odd count of planes starts one plane lower, whose
     // state reaches only warm-up planes.  Tiles of at least eight rows, which
     // hold the extra registers without spilling, also load the own column
     // one plane ahead, so that a plane's z arithmetic need not wait for
     // memory.  Otherwise one plane per trip.
-    constexpr bool TWO = NDIM == 3 && sizeof(T) == 4 && XF == 0;
+    constexpr bool TWO = NDIM == 3 && sizeof(T) == 4 && XF <= 1;
     constexpr bool ZPRE = TWO && TY >= 8;
     if constexpr (TWO) {
         T zn0 = 1, zn1 = 1, zn2 = 1;  // rho, m_z, rho*eps of the column, one plane ahead
